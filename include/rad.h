@@ -1,0 +1,176 @@
+/*
+ * rad.h - C ABI of the MI355X (gfx950) in-situ radiation-spectrum library.
+ *
+ * Computes, on the GPU, the spectrally resolved far-field radiation of PIC
+ * macro-particles with the form-factor weighting of Pausch et al., arXiv:1802.03972:
+ *
+ *   d^2I/(dOmega domega)(n, omega) =
+ *       C * | sum_j sum_m F_m(omega) A_{j,m}(n) exp(i omega (t_j - n.r_{j,m}/c)) |^2      (Eq. 13)
+ *
+ *   A = n x [(n - beta) x dbeta/dt] / (1 - beta.n)^2                                       (Eq. 1)
+ *   F_m(omega) = sqrt( N_m + (N_m^2 - N_m) g(omega) )                                      (Eqs. 11-12)
+ *   g = |F~(omega)|^2 of the normalised macro-particle shape                               (Table 1)
+ *   C = (q_e dt)^2 / (16 pi^3 eps0 c)   [J s / sr]
+ *
+ * The inner sum over macro-particles is accumulated step by step into a
+ * device-resident complex spectrum (the in-situ evaluation of Sec. 3.3), so memory is
+ * independent of the number of steps and particles.  |.|^2 is taken only when the
+ * spectrum is read.
+ *
+ * Conventions for every call:
+ *  - Return value: RAD_OK (0) or a negative RAD_ERR_* code; on error a message is
+ *    available from rad_last_error() (per calling thread) and outputs are untouched.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the device's null stream.
+ *    All work is stream-ordered.  Calls on one grid must be ordered on one stream (or
+ *    synchronised by the caller); concurrent calls on one grid from several streams race.
+ *  - Device pointers are plain device addresses on the grid's device, caller-owned.
+ *  - Units are SI: r [m], beta [1], dbeta/dt [1/s], N [electrons, real >= 0],
+ *    t and dt [s], omega [rad/s], shape length [m].
+ */
+#ifndef RAD_H
+#define RAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define RAD_OK               0
+#define RAD_ERR_INVALID_ARG (-1) /* a host-side argument check failed                   */
+#define RAD_ERR_OOM         (-2) /* device allocation failed                            */
+#define RAD_ERR_DEVICE      (-3) /* a HIP runtime call failed                           */
+#define RAD_ERR_BAD_DATA    (-4) /* device saw non-finite data, N < 0 or 1 - beta.n <= 0 */
+#define RAD_ERR_QUEUE_FULL  (-5) /* serving: request queue at capacity                  */
+
+/* ---- macro-particle shapes (Table 1; normalised so that g(0) = 1) ---- */
+#define RAD_SHAPE_POINT 0 /* g = 1 (all radiation coherent)                        */
+#define RAD_SHAPE_CIC   1 /* g = sinc^2(omega L / 2c), sinc(x) = sin(x)/x, L = cell  */
+#define RAD_SHAPE_TSC   2 /* g = sinc^4(omega L / 2c)                                */
+#define RAD_SHAPE_QSC   3 /* g = sinc^6(omega L / 2c)                                */
+#define RAD_SHAPE_GAUSS 4 /* g = exp(-omega^2 L^2 / c^2), rho ~ exp(-x^2 / 2 L^2)      */
+
+/* ---- arithmetic modes ---- */
+#define RAD_PHASE_F64 0 /* default: geometry and phase t - n.r/c in FP64, FP32 update */
+#define RAD_ALL_F32   1 /* everything in FP32 (precision study only)                 */
+
+/* ---- particle element types ---- */
+#define RAD_F32 0
+#define RAD_F64 1
+
+typedef struct rad_grid rad_grid;
+
+/* Observation grid of one spectrum (Eq. 13 is evaluated on every (n, omega) pair). */
+typedef struct rad_grid_desc {
+    int32_t n_dir;       /* number of directions, >= 1                                  */
+    const double* dirs;  /* HOST pointer, n_dir x 3 unit vectors (|n| within 1e-6 of 1);
+                            copied at creation                                          */
+    double omega0;       /* first frequency [rad/s], >= 0                               */
+    double domega;       /* uniform spacing [rad/s], >= 0; omega_k = omega0 + k*domega  */
+    int32_t n_omega;     /* number of frequencies, >= 1                                 */
+    int32_t shape;       /* RAD_SHAPE_*                                                  */
+    double shape_len;    /* cell width (CIC/TSC/QSC) or sigma (GAUSS) [m], > 0 unless POINT */
+    double dt;           /* time step of Eq. 13 [s], > 0 (enters the prefactor only)   */
+    int32_t precision;   /* RAD_PHASE_F64 or RAD_ALL_F32                                 */
+    int32_t device;      /* HIP device ordinal                                          */
+} rad_grid_desc;
+
+/* One batch of macro-particles, structure of arrays, all fields the same type. */
+typedef struct rad_particles {
+    int32_t dtype;                 /* RAD_F32 or RAD_F64                               */
+    const void *x, *y, *z;         /* position r [m]                                   */
+    const void *bx, *by, *bz;      /* velocity beta = v/c                              */
+    const void *dbx, *dby, *dbz;   /* dbeta/dt [1/s]                                   */
+    const void *w;                 /* weighting N (electrons per macro-particle)       */
+} rad_particles;
+
+/* Create a grid: copies the directions, builds the frequency and shape tables and a
+ * zeroed FP64 accumulator on `d->device`.  *out is written only on success. */
+int rad_create_grid(rad_grid** out, const rad_grid_desc* d);
+
+/* Release a grid.  Waits for the grid's device to finish outstanding work first.
+ * NULL is accepted (no-op). */
+int rad_destroy_grid(rad_grid* g);
+
+/* Zero the accumulated spectrum and clear the sticky data-error flag (stream-ordered). */
+int rad_reset(rad_grid* g, void* stream);
+
+/* Add one time step (Eq. 13 inner sum at t_j = t): for every (n, omega) of the grid,
+ * S += sum_{m<n_particles} F_m(omega) A_m(n) exp(i omega (t - n.r_m / c)).
+ * Particle arrays are device pointers of length n_particles and must stay valid until
+ * the stream passes this call.  n_particles == 0 is a no-op.  Data checked on the
+ * device (non-finite values, N < 0, 1 - beta.n <= 0) set a sticky flag that the next
+ * rad_spectrum / rad_spectrum_complex / rad_get_state reports as RAD_ERR_BAD_DATA. */
+int rad_push_step(rad_grid* g, double t, int64_t n_particles, const rad_particles* p,
+                  void* stream);
+
+/* Add n_steps consecutive steps at t_j = t0 + j*dt (dt of the grid), j = 0..n_steps-1.
+ * Arrays hold n_steps * n_particles elements, step-major (element j*n_particles + m).
+ * Same ownership and error behaviour as rad_push_step. */
+int rad_push_steps(rad_grid* g, double t0, int32_t n_steps, int64_t n_particles,
+                   const rad_particles* p, void* stream);
+
+/* Read d^2I/(dOmega domega) [J s/sr] into I_host (HOST, n_dir x n_omega doubles,
+ * row-major by direction).  Synchronises `stream`.  Non-destructive: accumulation may
+ * continue afterwards.  Returns RAD_ERR_BAD_DATA (and writes nothing) if the flag is set. */
+int rad_spectrum(rad_grid* g, double* I_host, void* stream);
+
+/* Same as rad_spectrum into a DEVICE buffer of n_dir x n_omega doubles, without
+ * synchronising; the data-error flag is not checked. */
+int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream);
+
+/* Read the complex spectrum S(n, omega) (without the prefactor) into S_host (HOST,
+ * n_dir x n_omega x 3 complex, interleaved re/im: index ((d*n_omega + k)*3 + c)*2).
+ * Synchronises `stream`. */
+int rad_spectrum_complex(rad_grid* g, double* S_host, void* stream);
+
+/* Number of doubles in the opaque accumulator state of this grid. */
+size_t rad_state_size(const rad_grid* g);
+
+/* Copy the accumulator state to / from HOST memory (rad_state_size doubles).  A state
+ * taken from one grid may be loaded into any grid with the same n_dir and n_omega.
+ * Both synchronise `stream`.  Used for checkpoint / resume. */
+int rad_get_state(rad_grid* g, double* state_host, void* stream);
+int rad_set_state(rad_grid* g, const double* state_host, void* stream);
+
+/* Per-thread message of the last failed call on this thread ("" if none). */
+const char* rad_last_error(void);
+
+/* Launch shape used by the accumulate kernel of a grid.
+ *   w_per_lane : frequencies held per lane (16 or 32)
+ *   dir_per_wave: directions per wavefront (16, 32 or 64)
+ *   waves      : wavefronts per workgroup (1..8)
+ *   wg_per_cu  : workgroups per compute unit the split count aims at (>= 1)
+ * rad_set_tile validates and applies it to later pushes. */
+typedef struct rad_tile {
+    int32_t w_per_lane;
+    int32_t dir_per_wave;
+    int32_t waves;
+    int32_t wg_per_cu;
+} rad_tile;
+int rad_get_tile(const rad_grid* g, rad_tile* t);
+int rad_set_tile(rad_grid* g, const rad_tile* t);
+
+/* Library and device facts: compute-unit count of `device`, or a negative code. */
+int rad_device_cus(int32_t device);
+
+/* Kernel timing of one grid.  While enabled, every accumulate launch and every fold
+ * launch of the grid is bracketed by HIP events recorded on the launch's own stream.
+ * rad_profile_read waits for the recorded events, returns the totals since the last read
+ * (or enable) and clears them.  Enabling adds two event records per launch. */
+typedef struct rad_profile_stats {
+    int64_t launches;        /* accumulate launches timed                               */
+    int64_t updates;         /* particle x direction x frequency terms in those launches */
+    double accumulate_ms;    /* summed accumulate kernel time [ms]                      */
+    double fold_ms;          /* summed fold kernel time [ms]                            */
+} rad_profile_stats;
+int rad_profile_enable(rad_grid* g, int enable);
+int rad_profile_read(rad_grid* g, rad_profile_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAD_H */

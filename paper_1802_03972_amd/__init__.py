@@ -1,0 +1,197 @@
+"""MI355X-native in-situ radiation spectra of PIC macro-particles with form factors.
+
+Python binding of librad.so (C ABI in include/rad.h); it only marshals arguments.  Every
+step of the computation runs in the library's HIP kernels.  torch supplies device buffers
+(`tensor.data_ptr()`) and streams (`torch.cuda.Stream.cuda_stream`).
+
+    g = Grid(dirs, omega0, domega, n_omega, shape="cic", shape_len=1e-7, dt=5e-17)
+    g.push_step(t, particles)          # dict of equal-length CUDA tensors x..dbz, w
+    I = g.spectrum()                   # (n_dir, n_omega) float64, J s / sr
+
+Equation references are to Pausch et al., arXiv:1802.03972: the sum is Eq. 13, the
+amplitude and phase Eq. 1, the form factor Eqs. 11-12, the shapes Table 1.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (RadError, SHAPES, PHASE_F64, ALL_F32, F32, F64, RAD_ERR_BAD_DATA,
+                   RAD_ERR_INVALID_ARG)
+
+FIELDS = ("x", "y", "z", "bx", "by", "bz", "dbx", "dby", "dbz", "w")
+
+
+def _stream_handle(stream, device: int):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_particles(fields: dict, expect_len: int | None = None, device: int | None = None):
+    """Validate a dict of CUDA tensors and return (rad_particles, n, keepalive)."""
+    import torch
+    ts = [fields[k] for k in FIELDS]
+    dt = ts[0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError(f"particle dtype must be float32 or float64, got {dt}")
+    n = ts[0].numel()
+    for k, t in zip(FIELDS, ts):
+        if not t.is_cuda:
+            raise TypeError(f"particle field {k} must be a CUDA tensor")
+        if t.dtype != dt:
+            raise TypeError(f"particle field {k} has dtype {t.dtype}, expected {dt}")
+        if not t.is_contiguous():
+            raise ValueError(f"particle field {k} must be contiguous")
+        if t.numel() != n:
+            raise ValueError(f"particle field {k} has {t.numel()} elements, expected {n}")
+        if device is not None and t.device.index != device:
+            raise ValueError(f"particle field {k} is on device {t.device.index}, grid is on {device}")
+    if expect_len is not None and n != expect_len:
+        raise ValueError(f"particle arrays hold {n} elements, expected {expect_len}")
+    p = _lib.Particles(F32 if dt == torch.float32 else F64, *[t.data_ptr() for t in ts])
+    return p, n, ts
+
+
+class Grid:
+    """One observation grid with its device-resident accumulated spectrum."""
+
+    def __init__(self, dirs, omega0: float, domega: float, n_omega: int, shape="cic",
+                 shape_len: float = 1e-7, dt: float = 5e-17, precision: int = PHASE_F64,
+                 device: int = 0):
+        L = _lib.lib()
+        self._dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+        self.n_dir = int(self._dirs.shape[0])
+        self.n_omega = int(n_omega)
+        self.device = int(device)
+        self.dt = float(dt)
+        self.omega0, self.domega = float(omega0), float(domega)
+        sid = SHAPES[shape] if isinstance(shape, str) else int(shape)
+        desc = _lib.GridDesc(self.n_dir, self._dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             self.omega0, self.domega, self.n_omega, sid, float(shape_len),
+                             self.dt, int(precision), self.device)
+        h = ctypes.c_void_p()
+        _lib.check(L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc)))
+        self._h = h
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().rad_destroy_grid(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    # ------------------------------------------------------------------ accumulate
+    def push_step(self, t: float, particles: dict, stream=None) -> None:
+        p, n, keep = make_particles(particles, device=self.device)
+        _lib.check(_lib.lib().rad_push_step(self._h, float(t), n, ctypes.byref(p),
+                                            _stream_handle(stream, self.device)))
+
+    def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
+        p, n, keep = make_particles(particles, device=self.device)
+        if n_steps <= 0 or n % n_steps:
+            raise ValueError("particle arrays must hold n_steps * n_particles elements")
+        _lib.check(_lib.lib().rad_push_steps(self._h, float(t0), int(n_steps), n // n_steps,
+                                             ctypes.byref(p), _stream_handle(stream, self.device)))
+
+    def reset(self, stream=None) -> None:
+        _lib.check(_lib.lib().rad_reset(self._h, _stream_handle(stream, self.device)))
+
+    # ------------------------------------------------------------------ read-out
+    def spectrum(self, stream=None) -> np.ndarray:
+        out = np.empty((self.n_dir, self.n_omega), np.float64)
+        _lib.check(_lib.lib().rad_spectrum(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           _stream_handle(stream, self.device)))
+        return out
+
+    def spectrum_device(self, out, stream=None):
+        """Write the spectrum into a CUDA float64 tensor of n_dir * n_omega elements."""
+        import torch
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != self.n_dir * self.n_omega \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA float64 tensor of n_dir*n_omega elements")
+        _lib.check(_lib.lib().rad_spectrum_device(self._h, ctypes.c_void_p(out.data_ptr()),
+                                                  _stream_handle(stream, self.device)))
+        return out
+
+    def spectrum_complex(self, stream=None) -> np.ndarray:
+        out = np.empty((self.n_dir, self.n_omega, 3, 2), np.float64)
+        _lib.check(_lib.lib().rad_spectrum_complex(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                   _stream_handle(stream, self.device)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    # ------------------------------------------------------------------ state
+    def state_size(self) -> int:
+        return int(_lib.lib().rad_state_size(self._h))
+
+    def get_state(self, stream=None) -> np.ndarray:
+        out = np.empty(self.state_size(), np.float64)
+        _lib.check(_lib.lib().rad_get_state(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _stream_handle(stream, self.device)))
+        return out
+
+    def set_state(self, state: np.ndarray, stream=None) -> None:
+        st = np.ascontiguousarray(state, np.float64)
+        if st.size != self.state_size():
+            raise ValueError(f"state has {st.size} doubles, grid needs {self.state_size()}")
+        _lib.check(_lib.lib().rad_set_state(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _stream_handle(stream, self.device)))
+
+    # ------------------------------------------------------------------ kernel timing
+    def profile(self, enable: bool = True) -> None:
+        _lib.check(_lib.lib().rad_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        st = _lib.ProfileStats()
+        _lib.check(_lib.lib().rad_profile_read(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.ProfileStats._fields_}
+
+    # ------------------------------------------------------------------ launch shape
+    def get_tile(self) -> dict:
+        t = _lib.Tile()
+        _lib.check(_lib.lib().rad_get_tile(self._h, ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in _lib.Tile._fields_}
+
+    def set_tile(self, **kw) -> None:
+        cur = self.get_tile()
+        cur.update(kw)
+        t = _lib.Tile(*[int(cur[k]) for k, _ in _lib.Tile._fields_])
+        _lib.check(_lib.lib().rad_set_tile(self._h, ctypes.byref(t)))
+
+
+def device_cus(device: int = 0) -> int:
+    rc = _lib.lib().rad_device_cus(int(device))
+    if rc < 0:
+        _lib.check(rc)
+    return rc
+
+
+def trig_probe(revs, stream=None):
+    """Hardware and library sin/cos of 2 pi r on the device (diagnostic)."""
+    import torch
+    x = torch.as_tensor(np.asarray(revs, np.float32), device="cuda").contiguous()
+    out = torch.empty(4 * x.numel(), dtype=torch.float32, device="cuda")
+    _lib.check(_lib.lib().rad_debug_trig_probe(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                               x.numel(), _stream_handle(stream, x.device.index)))
+    torch.cuda.synchronize()
+    return out.view(-1, 4).cpu().numpy()

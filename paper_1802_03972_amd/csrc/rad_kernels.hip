@@ -1,0 +1,422 @@
+// gfx950 kernels of the in-situ macro-particle radiation sum (arXiv:1802.03972, Eq. 13).
+//
+// Work decomposition of the accumulate kernel
+// -------------------------------------------
+// One update is one (macro-particle m, direction n, frequency omega) term
+//     S(n, omega) += F_m(omega) * A_m(n) * exp(i omega tau_m(n)),   tau = t - n.r/c.
+// * A lane owns ONE direction and W consecutive frequencies; its W complex spectrum
+//   entries live in registers for the whole launch.
+// * Since A = n x [...] is normal to n, it is stored in a fixed per-direction basis
+//   (e1, e2) of the plane normal to n: two real components instead of three, and the
+//   spectrum holds two complex components.  |S|^2 is unchanged and the Cartesian
+//   spectrum is e1*S1 + e2*S2.
+// * A workgroup owns a tile of TD directions x TO frequencies and a contiguous range of
+//   particles (its split).  Particles stream through LDS in chunks of kChunk:
+//     1. coalesced SoA load of the chunk into LDS (widened to FP64);
+//     2. per (particle, direction) geometry in FP64 -- 1 - beta.n without cancellation,
+//        A in the (e1, e2) basis, tau/(2 pi), the rotation w = exp(i domega tau) --
+//        shared by the workgroup's TO frequencies;
+//     3. per (particle, frequency) form-factor weight F = sqrt(N (1-g) + N^2 g) (Eq. 12),
+//        shared by the workgroup's TD directions;
+//     4. the hot loop: per particle, each lane seeds z = exp(i omega_first tau) from the
+//        FP64 phase (reduced to [0, 1) revolutions before leaving FP64), then walks its W
+//        frequencies with z <- z*w (uniform omega grid), scaling by F and accumulating.
+//        10 FP32 VALU operations per update: 2 (scale) + 4 (two complex FMAs) + 4 (rotate).
+// * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
+//   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "rad_internal.h"
+
+namespace rad {
+
+namespace {
+
+constexpr double kInvC = 1.0 / 299792458.0;          // 1/c [s/m]
+constexpr double kInv2Pi = 0.15915494309189533577;   // 1/(2 pi)
+
+// sin and cos of 2*pi*r, r in revolutions (the hardware transcendental takes revolutions).
+__device__ __forceinline__ void sincos_rev_fast(float r, float& s, float& c)
+{
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
+// Library sin/cos(pi x) (few-ulp accurate); used where the result is reused many times.
+__device__ __forceinline__ void sincos_rev_accurate(float r, float& s, float& c)
+{
+    sincospif(2.0f * r, &s, &c);
+}
+
+__device__ __forceinline__ void flag_error(int* err)
+{
+    atomicOr(err, 1);
+}
+
+template <typename InT>
+__device__ __forceinline__ double load_wide(const void* p, int64_t i)
+{
+    return static_cast<double>(static_cast<const InT*>(p)[i]);
+}
+
+// Per (particle, direction) geometry.  Writes A1, A2 (FP32), w = exp(i domega tau) and
+// tau/(2 pi) (FP64).
+template <int PREC>
+__device__ __forceinline__ void particle_direction_setup(const double* __restrict__ raw, int m,
+                                                         const double* __restrict__ dv,
+                                                         double domega, float4& geo,
+                                                         double& ph_out, int* err)
+{
+    constexpr int P = kChunk;
+    const double x = raw[0 * P + m], y = raw[1 * P + m], z = raw[2 * P + m];
+    const double bx = raw[3 * P + m], by = raw[4 * P + m], bz = raw[5 * P + m];
+    const double dbx = raw[6 * P + m], dby = raw[7 * P + m], dbz = raw[8 * P + m];
+    const double N = raw[9 * P + m], t = raw[10 * P + m];
+    const double nx = dv[0], ny = dv[1], nz = dv[2];
+    const double e1x = dv[3], e1y = dv[4], e1z = dv[5];
+    const double e2x = dv[6], e2y = dv[7], e2z = dv[8];
+    float A1, A2, wr, wi;
+    double ph;
+    bool bad;
+    if constexpr (PREC == 0) {
+        // A = [(n - beta)(n.dbeta) - dbeta (1 - beta.n)] / (1 - beta.n)^2, projected on e1, e2
+        // (n.e = 0 removes the n term).  FP64 keeps 1 - beta.n ~ 1/(2 gamma^2) accurate.
+        const double D = 1.0 - (bx * nx + by * ny + bz * nz);
+        const double nbd = nx * dbx + ny * dby + nz * dbz;
+        const double b1 = bx * e1x + by * e1y + bz * e1z;
+        const double b2 = bx * e2x + by * e2y + bz * e2z;
+        const double q1 = dbx * e1x + dby * e1y + dbz * e1z;
+        const double q2 = dbx * e2x + dby * e2y + dbz * e2z;
+        const double inv = 1.0 / (D * D);
+        const double a1 = -(b1 * nbd + q1 * D) * inv;
+        const double a2 = -(b2 * nbd + q2 * D) * inv;
+        const double tau = t - (nx * x + ny * y + nz * z) * kInvC;
+        ph = tau * kInv2Pi;
+        double rw = domega * ph;
+        rw -= floor(rw);
+        sincos_rev_accurate(static_cast<float>(rw), wi, wr);
+        A1 = static_cast<float>(a1);
+        A2 = static_cast<float>(a2);
+        bad = !(D > 0.0) || !(N >= 0.0) || !isfinite(N) || !isfinite(ph) || !isfinite(A1) ||
+              !isfinite(A2);
+    } else {
+        // All-FP32 variant (precision study): same formulas on FP32-rounded values.
+        const float fx = (float)x, fy = (float)y, fz = (float)z;
+        const float fbx = (float)bx, fby = (float)by, fbz = (float)bz;
+        const float fdbx = (float)dbx, fdby = (float)dby, fdbz = (float)dbz;
+        const float fnx = (float)nx, fny = (float)ny, fnz = (float)nz;
+        const float f1x = (float)e1x, f1y = (float)e1y, f1z = (float)e1z;
+        const float f2x = (float)e2x, f2y = (float)e2y, f2z = (float)e2z;
+        const float D = 1.0f - (fbx * fnx + fby * fny + fbz * fnz);
+        const float nbd = fnx * fdbx + fny * fdby + fnz * fdbz;
+        const float b1 = fbx * f1x + fby * f1y + fbz * f1z;
+        const float b2 = fbx * f2x + fby * f2y + fbz * f2z;
+        const float q1 = fdbx * f1x + fdby * f1y + fdbz * f1z;
+        const float q2 = fdbx * f2x + fdby * f2y + fdbz * f2z;
+        const float inv = 1.0f / (D * D);
+        A1 = -(b1 * nbd + q1 * D) * inv;
+        A2 = -(b2 * nbd + q2 * D) * inv;
+        const float tau = (float)t - (fnx * fx + fny * fy + fnz * fz) * (float)kInvC;
+        const float phf = tau * (float)kInv2Pi;
+        float rw = (float)domega * phf;
+        rw -= floorf(rw);
+        sincos_rev_accurate(rw, wi, wr);
+        ph = (double)phf;
+        bad = !(D > 0.0f) || !(N >= 0.0) || !isfinite(N) || !isfinite(phf) || !isfinite(A1) ||
+              !isfinite(A2);
+    }
+    if (bad) flag_error(err);
+    geo = make_float4(A1, A2, wr, wi);
+    ph_out = ph;
+}
+
+template <typename InT, int PREC, int W, int DPW>
+__global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
+{
+    constexpr int P = kChunk;
+    constexpr int SUBS = 64 / DPW;
+    constexpr int TD = DPW;
+    static_assert(W % 4 == 0, "W must be a multiple of 4");
+
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int waves = nt >> 6;
+    const int TO = waves * SUBS * W;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int dl = lane % DPW;
+    const int ob = wave * SUBS + lane / DPW;
+
+    const int ntiles = a.tiles_d * a.tiles_w;
+    const int tile = blockIdx.x % ntiles;
+    const int split = blockIdx.x / ntiles;
+    const int td = tile % a.tiles_d;
+    const int tw = tile / a.tiles_d;
+
+    extern __shared__ float4 smem4[];
+    float4* geo = smem4;                                             // [P][TD]
+    double* taus = reinterpret_cast<double*>(geo + P * TD);          // [P][TD]
+    double* raw = taus + P * TD;                                     // [11][P]
+    float* ff = reinterpret_cast<float*>(raw + 11 * P);              // [P][TO]
+
+    const int d = td * TD + dl;
+    const int o_first = tw * TO + ob * W;
+    const double om_first = a.omega[o_first < a.n_omega ? o_first : a.n_omega - 1];
+
+    float s1r[W], s1i[W], s2r[W], s2i[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        s1r[k] = 0.f; s1i[k] = 0.f; s2r[k] = 0.f; s2i[k] = 0.f;
+    }
+
+    const int64_t n_local = a.i_end - a.i_begin;
+    const int64_t nchunks = (n_local + P - 1) / P;
+    const int64_t c_begin = (int64_t)split * a.chunks_per_split;
+    int64_t c_end = c_begin + a.chunks_per_split;
+    if (c_end > nchunks) c_end = nchunks;
+
+    for (int64_t c = c_begin; c < c_end; ++c) {
+        // 1. stage the chunk (SoA, coalesced), widened to FP64, plus the step time.
+        if (tid < P) {
+            const int64_t i = a.i_begin + c * P + tid;
+            const bool ok = i < a.i_end;
+            const int64_t ii = ok ? i : a.i_begin;
+#pragma unroll
+            for (int f = 0; f < 10; ++f) raw[f * P + tid] = ok ? load_wide<InT>(a.f[f], ii) : 0.0;
+            const int64_t step = ii / a.n_per_step;
+            raw[10 * P + tid] = ok ? a.t0 + (double)step * a.dt : 0.0;
+        }
+        __syncthreads();
+        // 2. per (particle, direction) geometry.
+        for (int i = tid; i < P * TD; i += nt) {
+            const int m = i / TD;
+            int dg = td * TD + (i % TD);
+            dg = dg < a.n_dir ? dg : a.n_dir - 1;
+            float4 gv;
+            double ph;
+            particle_direction_setup<PREC>(raw, m, a.dirs9 + 9 * dg, a.domega, gv, ph, a.err);
+            geo[i] = gv;
+            taus[i] = ph;
+        }
+        // 3. per (particle, frequency) form-factor weight (Eq. 12), FP32.
+        for (int i = tid; i < P * TO; i += nt) {
+            const int m = i / TO;
+            const int og = tw * TO + (i % TO);
+            float F = 0.f;
+            if (og < a.n_omega) {
+                const float N = (float)raw[9 * P + m];
+                const float2 g = a.gtab[og];
+                F = __builtin_sqrtf(fmaf(N * N, g.x, N * g.y));
+            }
+            ff[i] = F;
+        }
+        __syncthreads();
+        // 4. hot loop.
+        for (int m = 0; m < P; ++m) {
+            const float4 gm = geo[m * TD + dl];
+            const double ph = taus[m * TD + dl];
+            float zr, zi;
+            if constexpr (PREC == 0) {
+                double rv = om_first * ph;
+                rv -= floor(rv);
+                sincos_rev_fast(static_cast<float>(rv), zi, zr);
+            } else {
+                float rv = (float)om_first * (float)ph;
+                rv -= floorf(rv);
+                sincos_rev_fast(rv, zi, zr);
+            }
+            const float A1 = gm.x, A2 = gm.y, wr = gm.z, wi = gm.w;
+            const float4* fq = reinterpret_cast<const float4*>(ff + m * TO + ob * W);
+#pragma unroll
+            for (int q = 0; q < W / 4; ++q) {
+                const float4 F4 = fq[q];
+                const float Fv[4] = {F4.x, F4.y, F4.z, F4.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = 4 * q + u;
+                    const float ur = Fv[u] * zr;
+                    const float ui = Fv[u] * zi;
+                    s1r[k] = fmaf(A1, ur, s1r[k]);
+                    s1i[k] = fmaf(A1, ui, s1i[k]);
+                    s2r[k] = fmaf(A2, ur, s2r[k]);
+                    s2i[k] = fmaf(A2, ui, s2i[k]);
+                    const float nr = fmaf(zr, wr, -(zi * wi));
+                    const float ni = fmaf(zr, wi, zi * wr);
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // 5. per-workgroup partial tile, layout [split][omega][dir][4] (coalesced over dir).
+    if (d < a.n_dir) {
+        float4* out = reinterpret_cast<float4*>(a.part);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int og = o_first + k;
+            if (og < a.n_omega)
+                out[((int64_t)split * a.n_omega + og) * a.n_dir + d] =
+                    make_float4(s1r[k], s1i[k], s2r[k], s2i[k]);
+        }
+    }
+}
+
+// S[i] += sum over splits of part[s][i], in split order, in FP64.
+__global__ void k_fold(const float* __restrict__ part, double* __restrict__ S, int splits,
+                       int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += (double)part[(int64_t)k * count + i];
+    S[i] += s;
+}
+
+// I[d][k] = C * (|S1|^2 + |S2|^2), S layout [omega][dir][4].
+__global__ void k_finalize(const double* __restrict__ S, double* __restrict__ I, int n_dir,
+                           int n_omega, double C)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_dir * n_omega) return;
+    const int d = (int)(i / n_omega), k = (int)(i % n_omega);
+    const double* s = S + ((int64_t)k * n_dir + d) * 4;
+    I[i] = C * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + s[3] * s[3]);
+}
+
+// Cartesian complex spectrum out[((d*n_omega + k)*3 + c)*2 + {re, im}] = e1_c S1 + e2_c S2.
+__global__ void k_cartesian(const double* __restrict__ S, const double* __restrict__ dirs9,
+                            double* __restrict__ out, int n_dir, int n_omega)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_dir * n_omega) return;
+    const int d = (int)(i / n_omega), k = (int)(i % n_omega);
+    const double* s = S + ((int64_t)k * n_dir + d) * 4;
+    const double* e = dirs9 + 9 * d;
+    for (int c = 0; c < 3; ++c) {
+        out[(i * 3 + c) * 2 + 0] = e[3 + c] * s[0] + e[6 + c] * s[2];
+        out[(i * 3 + c) * 2 + 1] = e[3 + c] * s[1] + e[6 + c] * s[3];
+    }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// out[4i..4i+3] = hardware sin/cos and library sin/cos of 2*pi*in[i].
+__global__ void k_trig_probe(const float* in, float* out, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s, c, s2, c2;
+    sincos_rev_fast(in[i], s, c);
+    sincos_rev_accurate(in[i], s2, c2);
+    out[4 * i + 0] = s;
+    out[4 * i + 1] = c;
+    out[4 * i + 2] = s2;
+    out[4 * i + 3] = c2;
+}
+
+inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename InT, int PREC, int W, int DPW>
+hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+{
+    auto kern = k_accumulate<InT, PREC, W, DPW>;
+    const size_t lds = acc_lds_bytes(s);
+    static size_t lds_allowed = 64 * 1024;  // per instantiation; the attribute is process-wide
+    if (lds > lds_allowed) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_allowed = lds;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename InT, int PREC>
+hipError_t launch_acc_p(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+{
+    if (s.w_per_lane == 32) {
+        if (s.dir_per_wave == 64) return launch_acc_t<InT, PREC, 32, 64>(a, s, n_blocks, st);
+        if (s.dir_per_wave == 32) return launch_acc_t<InT, PREC, 32, 32>(a, s, n_blocks, st);
+        if (s.dir_per_wave == 16) return launch_acc_t<InT, PREC, 32, 16>(a, s, n_blocks, st);
+    } else if (s.w_per_lane == 16) {
+        if (s.dir_per_wave == 64) return launch_acc_t<InT, PREC, 16, 64>(a, s, n_blocks, st);
+        if (s.dir_per_wave == 32) return launch_acc_t<InT, PREC, 16, 32>(a, s, n_blocks, st);
+        if (s.dir_per_wave == 16) return launch_acc_t<InT, PREC, 16, 16>(a, s, n_blocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
+                             int n_blocks, hipStream_t st)
+{
+    if (dtype == 0) {
+        return precision == 0 ? launch_acc_p<float, 0>(a, s, n_blocks, st)
+                              : launch_acc_p<float, 1>(a, s, n_blocks, st);
+    }
+    return precision == 0 ? launch_acc_p<double, 0>(a, s, n_blocks, st)
+                          : launch_acc_p<double, 1>(a, s, n_blocks, st);
+}
+
+hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fold, dim3(grid1d(count, 256)), dim3(256), 0, st, part, S, splits, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* S, double* I, int n_dir, int n_omega, double C,
+                           hipStream_t st)
+{
+    const int64_t n = (int64_t)n_dir * n_omega;
+    hipLaunchKernelGGL(k_finalize, dim3(grid1d(n, 256)), dim3(256), 0, st, S, I, n_dir, n_omega, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_cartesian(const double* S, const double* dirs9, double* out, int n_dir,
+                            int n_omega, hipStream_t st)
+{
+    const int64_t n = (int64_t)n_dir * n_omega;
+    hipLaunchKernelGGL(k_cartesian, dim3(grid1d(n, 256)), dim3(256), 0, st, S, dirs9, out, n_dir,
+                       n_omega);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid1d(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3(grid1d(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_trig_probe(const float* in, float* out, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trig_probe, dim3(grid1d(n, 256)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace rad

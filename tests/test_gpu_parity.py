@@ -1,0 +1,259 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, element by element.
+
+Metric: e_inf = max |I_gpu - I_oracle| / max I_oracle (relative tolerance 1e-4 on the
+spectrum, taken against the spectrum's peak so that nulls do not dominate).  The oracle
+always consumes exactly the values the device ingests (float32 configs are rounded
+before both sides see them).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import TINY, SINGLE, PRECISION, circular_orbit, flatten, replicate, Workload
+from tests.helpers import e_inf, to_device, step_slice
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rad():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1802_03972_amd as rad
+    rad._lib.lib()
+    return rad
+
+
+def make_grid(rad, w: Workload, **kw):
+    return rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
+                    shape_len=w.shape_len, dt=w.dt, **kw)
+
+
+def run_gpu(rad, w: Workload, steps: dict, per_step=True, grid=None, **kw):
+    g = grid or make_grid(rad, w, **kw)
+    dev = to_device(steps, w.in_dtype)
+    n = steps["x"].shape[1]
+    times = w.times(0, steps["x"].shape[0])
+    if per_step:
+        for j, t in enumerate(times):
+            g.push_step(float(t), step_slice(dev, j, n))
+    else:
+        g.push_steps(float(times[0]), len(times), dev)
+    return g
+
+
+def oracle_I(w: Workload, steps: dict, dirs=None, omegas=None):
+    times = w.times(0, steps["x"].shape[0])
+    return oracle.spectrum(flatten(steps, times), w.directions() if dirs is None else dirs,
+                           w.omegas() if omegas is None else omegas, w.shape, w.shape_len, w.dt)
+
+
+# ----------------------------------------------------------------------------- builtins
+def test_trig_builtins_take_revolutions(rad):
+    r = np.linspace(0.0, 1.0, 4097, dtype=np.float32)[:-1]
+    out = rad.trig_probe(r)
+    ref_s, ref_c = np.sin(2 * np.pi * r.astype(np.float64)), np.cos(2 * np.pi * r.astype(np.float64))
+    err_hw = max(np.abs(out[:, 0] - ref_s).max(), np.abs(out[:, 1] - ref_c).max())
+    err_lib = max(np.abs(out[:, 2] - ref_s).max(), np.abs(out[:, 3] - ref_c).max())
+    print(f"hardware sin/cos(2 pi r) max abs err {err_hw:.3e}; library sincospi {err_lib:.3e}")
+    assert err_lib < 5e-7
+    assert err_hw < 1e-5
+
+
+# ----------------------------------------------------------------------------- parity
+def test_tiny_config_full_grid(rad):
+    """1024 macro-particles x 64 steps, 4x4 directions x 64 omega, FP64 input, Gauss."""
+    w = TINY
+    st = w.steps()
+    g = run_gpu(rad, w, st)
+    I = g.spectrum()
+    Iref = oracle_I(w, st)
+    err = e_inf(I, Iref)
+    print(f"tiny: e_inf = {err:.3e}")
+    assert err <= TOL
+    S = g.spectrum_complex()
+    Sref = oracle.spectrum_complex(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len)
+    assert np.max(np.abs(S - Sref)) <= TOL * np.max(np.abs(Sref))
+
+
+@pytest.mark.parametrize("shape,dtype", [("cic", "f32"), ("tsc", "f64"), ("qsc", "f32"),
+                                         ("gauss", "f64"), ("point", "f32")])
+def test_ragged_tiles(rad, shape, dtype):
+    """Sizes that leave ragged tails in every dimension: 5x8 directions, 100 omega,
+    1000 particles (not a multiple of the 32-particle chunk), 3 steps."""
+    w = SINGLE.scaled(n_particles=1000, n_steps=3, nx_dir=5, ny_dir=8, n_omega=100,
+                      omega_max=4e18, shape=shape, in_dtype=dtype, seed=21)
+    st = w.steps()
+    I = run_gpu(rad, w, st).spectrum()
+    err = e_inf(I, oracle_I(w, st))
+    print(f"ragged {shape}/{dtype}: e_inf = {err:.3e}")
+    assert err <= TOL
+
+
+def test_every_tile_shape_agrees(rad):
+    w = SINGLE.scaled(n_particles=700, n_steps=2, nx_dir=6, ny_dir=7, n_omega=150, omega_max=6e18, seed=5)
+    st = w.steps()
+    Iref = oracle_I(w, st)
+    for wpl in (16, 32):
+        for dpw in (16, 32, 64):
+            for waves in (1, 2, 4, 8):
+                g = make_grid(rad, w)
+                g.set_tile(w_per_lane=wpl, dir_per_wave=dpw, waves=waves, wg_per_cu=1)
+                I = run_gpu(rad, w, st, grid=g).spectrum()
+                err = e_inf(I, Iref)
+                assert err <= TOL, (wpl, dpw, waves, err)
+                g.close()
+
+
+def test_push_steps_matches_per_step_pushes(rad):
+    w = TINY.scaled(n_particles=300, n_steps=5, seed=2)
+    st = w.steps()
+    I1 = run_gpu(rad, w, st, per_step=True).spectrum()
+    I2 = run_gpu(rad, w, st, per_step=False).spectrum()
+    assert e_inf(I2, I1) <= 1e-6
+    assert e_inf(I2, oracle_I(w, st)) <= TOL
+
+
+def test_chunk_linearity(rad):
+    """Splitting one step's particles over two pushes changes only the rounding."""
+    w = SINGLE.scaled(n_particles=2000, n_steps=1, nx_dir=4, ny_dir=8, n_omega=128, seed=8)
+    st = w.steps()
+    dev = to_device(st, w.in_dtype)
+    g1 = make_grid(rad, w)
+    g1.push_step(0.0, dev)
+    g2 = make_grid(rad, w)
+    g2.push_step(0.0, {k: v[:777] for k, v in dev.items()})
+    g2.push_step(0.0, {k: v[777:] for k, v in dev.items()})
+    assert e_inf(g2.spectrum(), g1.spectrum()) <= 1e-6
+
+
+def test_deterministic_repeat(rad):
+    w = SINGLE.scaled(n_particles=5000, n_steps=2, nx_dir=8, ny_dir=8, n_omega=256, seed=9)
+    st = w.steps()
+    a = run_gpu(rad, w, st).spectrum()
+    b = run_gpu(rad, w, st).spectrum()
+    assert np.array_equal(a, b)
+
+
+def test_time_shift_invariance_fp64_phase(rad):
+    """t -> t + 1 ps with r unchanged multiplies S by exp(i omega T): I unchanged."""
+    w = PRECISION.scaled(n_particles=512, n_steps=4, n_omega=256, omega_max=1e20, t0=0.0, seed=4)
+    st = w.steps()
+    I0 = run_gpu(rad, w, st).spectrum()
+    w1 = w.scaled(t0=1e-12)
+    I1 = run_gpu(rad, w1, st).spectrum()
+    err = e_inf(I1, I0)
+    print(f"time shift 1 ps: e_inf = {err:.3e}")
+    assert err <= TOL
+
+
+def test_checkpoint_resume(rad):
+    w = SINGLE.scaled(n_particles=1500, n_steps=4, nx_dir=4, ny_dir=4, n_omega=64, seed=3)
+    st = w.steps()
+    dev = to_device(st, w.in_dtype)
+    n = w.n_particles
+    times = w.times()
+    g = make_grid(rad, w)
+    for j in range(4):
+        g.push_step(float(times[j]), step_slice(dev, j, n))
+    full = g.get_state()
+    g2 = make_grid(rad, w)
+    for j in range(2):
+        g2.push_step(float(times[j]), step_slice(dev, j, n))
+    saved = g2.get_state()
+    g3 = make_grid(rad, w)
+    g3.set_state(saved)
+    for j in range(2, 4):
+        g3.push_step(float(times[j]), step_slice(dev, j, n))
+    assert np.array_equal(g3.get_state(), full)
+    g.reset()
+    assert np.all(g.spectrum() == 0.0)
+
+
+def test_bad_data_sets_sticky_flag(rad):
+    import torch
+    w = TINY.scaled(n_particles=64, n_steps=1, seed=1)
+    st = w.steps()
+    dev = to_device(st, "f64")
+    dev["bx"][5] = float("nan")
+    g = make_grid(rad, w)
+    g.push_step(0.0, dev)
+    with pytest.raises(rad.RadError) as ei:
+        g.spectrum()
+    assert ei.value.code == rad.RAD_ERR_BAD_DATA
+    g.reset()
+    dev2 = to_device(st, "f64")
+    dev2["bz"][3] = 1.0  # beta along n ~ 1: 1 - beta.n <= 0 for the on-axis direction
+    dev2["bx"][3] = 0.0
+    dev2["by"][3] = 0.0
+    g2 = rad.Grid(np.array([[0.0, 0.0, 1.0]]), 0.0, 1e16, 8, shape="gauss", shape_len=1e-7, dt=w.dt)
+    g2.push_step(0.0, dev2)
+    with pytest.raises(rad.RadError):
+        g2.spectrum()
+    g2.reset()
+    g2.push_step(0.0, to_device(st, "f64"))
+    assert np.all(np.isfinite(g2.spectrum()))
+    torch.cuda.synchronize()
+
+
+def test_empty_push_is_noop(rad):
+    import torch
+    w = TINY.scaled(n_particles=32, n_steps=1)
+    g = make_grid(rad, w)
+    empty = {k: torch.empty(0, dtype=torch.float64, device="cuda") for k in rad.FIELDS}
+    g.push_step(0.0, empty)
+    assert np.all(g.spectrum() == 0.0)
+
+
+def test_circular_orbit_harmonics_gpu(rad):
+    """One electron on a circular orbit: device spectrum at the harmonics vs the oracle
+    (which itself matches the Bessel closed form)."""
+    beta, w0, K, Np = 0.9, 1e13, 512, 2
+    dt = 2 * np.pi / w0 / K
+    times = np.arange(K * Np) * dt
+    tr = circular_orbit(beta, w0, times)
+    th = np.array([0.3, 0.7, 1.2])
+    dirs = np.stack([np.sin(th), 0 * th, np.cos(th)], 1)
+    g = rad.Grid(dirs, 0.0, w0, 12, shape="point", shape_len=0.0, dt=dt)
+    dev = to_device(tr, "f64")
+    g.push_steps(0.0, K * Np, dev)
+    I = g.spectrum()
+    Iref = oracle.spectrum(flatten(tr, times), dirs, np.arange(12) * w0, "point", 0.0, dt)
+    err = e_inf(I[:, 1:], Iref[:, 1:])
+    print(f"circular orbit: e_inf = {err:.3e}")
+    assert err <= TOL
+
+
+def test_coherent_and_incoherent_limits_gpu(rad):
+    w = TINY.scaled(n_particles=1, n_steps=32, seed=7)
+    st1 = w.steps()
+    Ns = np.array([3.0, 17.5, 120.0, 1e4])
+    stM = replicate(st1, Ns)
+    one = dict(st1); one["w"] = np.ones_like(st1["w"])
+    for shape, expect in (("point", Ns.sum() ** 2), ):
+        ww = w.scaled(shape=shape, n_particles=len(Ns))
+        I1 = run_gpu(rad, w.scaled(shape=shape), one).spectrum()
+        IM = run_gpu(rad, ww, stM).spectrum()
+        assert e_inf(IM, expect * I1) <= TOL
+    # g = 0 exactly for omega > 0 (very wide Gaussian): a single macro-particle gives N * I1
+    wg = w.scaled(shape="gauss", shape_len=1.0)
+    N = 4321.0
+    macro = dict(st1); macro["w"] = np.full_like(st1["w"], N)
+    I1 = run_gpu(rad, wg, one).spectrum()[:, 1:]
+    IN = run_gpu(rad, wg, macro).spectrum()[:, 1:]
+    assert e_inf(IN, N * I1) <= TOL
+
+
+def test_single_bunch_full_size_sampled(rad):
+    """One full-size step of the 65536-particle single-bunch workload (launch shape of the
+    bench), checked against the oracle on every direction and every 16th frequency."""
+    w = SINGLE.scaled(n_steps=1)
+    st = w.steps()
+    I = run_gpu(rad, w, st).spectrum()
+    sel = np.arange(0, w.n_omega, 16)
+    Iref = oracle_I(w, st, omegas=w.omegas()[sel])
+    err = e_inf(I[:, sel], Iref)
+    print(f"single bunch full size (1 step), sampled: e_inf = {err:.3e}")
+    assert err <= TOL
