@@ -33,11 +33,31 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single_bunch_fp32", choices=["single_bunch_fp32", "tiny_fp64"])
+    ap.add_argument("--workload", default="single_bunch_fp32",
+                    choices=["single_bunch_fp32", "tiny_fp64", "batched_uneven"])
+    ap.add_argument("--distinct-steps", type=int, default=8,
+                    help="batched_uneven: distinct generated steps per bunch, cycled over its 200 steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-pushes", type=int, default=100)
     ap.add_argument("--tile", default="", help="override launch shape: w_per_lane,dir_per_wave,waves,wg_per_cu")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain streaming kernel (read MIB, write MIB) to scale HBM byte counters")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int) -> int:
+    """dst = src * 1 over `mib` MiB of float32: one read and one write of known size per
+    dispatch, the reference for scaling FETCH_SIZE / WRITE_SIZE counter readings."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": n * 4, "bytes_written_per_dispatch": n * 4,
+                      "dispatches": 5}), flush=True)
+    return 0
 
 
 def log(msg: str) -> None:
@@ -46,6 +66,8 @@ def log(msg: str) -> None:
 
 def main() -> int:
     args = parse()
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -58,6 +80,9 @@ def main() -> int:
 
     import paper_1802_03972_amd as rad
     from workloads import SINGLE, TINY, flatten
+
+    if args.workload == "batched_uneven":
+        return bench_batched(args)
 
     w = SINGLE if args.workload == "single_bunch_fp32" else TINY
     dev_id = 0
@@ -133,11 +158,13 @@ def main() -> int:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         g.push_step(float(times[j]), slices[j], stream)
-        stream.synchronize()
+        torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
-    lat = np.array(lat)
-    latency = {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
-               "unit": "ms", "what": f"one time-step push of {n} particles (accumulate + fold), host-timed"}
+    latency = None
+    if lat:
+        lat = np.array(lat)
+        latency = {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                   "unit": "ms", "what": f"one time-step push of {n} particles (accumulate + fold), host-timed"}
 
     # ---- FP64 CPU oracle on a bounded sample, and device parity on the same sample
     cpu = None
@@ -181,6 +208,91 @@ def main() -> int:
         "parity": parity,
     }
     g.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batched(args) -> int:
+    """12 independent bunches (log-uniform counts in [1e3, 5e5]), each with its own 8x8 x 256
+    grid, 200 steps.  Per step: either 12 per-bunch pushes (one launch pair each) or one
+    batched persistent launch over all 12 bunches.  Same data, same grids."""
+    import numpy as np
+    import torch
+
+    import paper_1802_03972_amd as rad
+    from workloads import batched_uneven
+
+    mb = batched_uneven()
+    ws = mb.bunches()
+    n_steps = ws[0].n_steps
+    kd = max(1, min(args.distinct_steps, n_steps))
+    log(f"[bench] batched_uneven: counts {list(mb.counts)}, {n_steps} steps ({kd} distinct generated steps cycled)")
+    devs, grids = [], []
+    for w in ws:
+        st = w.steps(0, kd)
+        devs.append({k: torch.as_tensor(np.ascontiguousarray(st[k]).reshape(-1)).to("cuda:0", torch.float32)
+                     for k in rad.FIELDS})
+        grids.append(rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
+                              shape_len=w.shape_len, dt=w.dt))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(0)
+    batcher = rad.Batcher(max_items=len(ws))
+    slices = [[{k: v[j * w.n_particles:(j + 1) * w.n_particles] for k, v in d.items()} for j in range(kd)]
+              for w, d in zip(ws, devs)]
+    times = ws[0].times()
+    updates = sum(w.n_particles for w in ws) * n_steps * ws[0].n_dir * ws[0].n_omega
+
+    def per_bunch():
+        for g in grids:
+            g.reset(stream)
+        for j in range(n_steps):
+            for b, g in enumerate(grids):
+                g.push_step(float(times[j]), slices[b][j % kd], stream)
+
+    def batched():
+        for g in grids:
+            g.reset(stream)
+        for j in range(n_steps):
+            batcher.push([(g, float(times[j]), 1, slices[b][j % kd]) for b, g in enumerate(grids)], stream)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    reps = max(1, args.steps)
+    t_pb = timed(per_bunch, reps)
+    log(f"[bench] per-bunch launches: {t_pb * 1e3:.1f} ms per {n_steps} steps ({updates / t_pb:.4e} updates/s)")
+    I_pb = [g.spectrum() for g in grids]
+    batcher.profile(True)
+    t_b = timed(batched, reps)
+    prof = batcher.profile_read()
+    batcher.profile(False)
+    log(f"[bench] batched persistent: {t_b * 1e3:.1f} ms per {n_steps} steps ({updates / t_b:.4e} updates/s)")
+    I_b = [g.spectrum() for g in grids]
+    agree = max(float(np.max(np.abs(a - b)) / np.max(a)) for a, b in zip(I_pb, I_b))
+    avg_ms = prof["accumulate_ms"] / max(1, prof["launches"])
+    achieved = prof["updates"] / max(1, prof["launches"]) * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
+    out = {
+        "metric": "particle*direction*frequency updates/s (vs FP32 peak); p50/p99 step latency",
+        "value": updates / t_b, "unit": "updates/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": t_b * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_uneven", "bunches": len(ws), "counts": list(mb.counts),
+                   "time_steps": n_steps, "directions": ws[0].n_dir, "frequencies": ws[0].n_omega,
+                   "distinct_generated_steps": kd, "updates_per_step": updates, "tile": grids[0].get_tile()},
+        "per_bunch_launches": {"value": updates / t_pb, "ms_per_step": t_pb * 1e3},
+        "speedup_vs_per_bunch": t_pb / t_b,
+        "batched_vs_per_bunch_e_inf": agree,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_accumulate_batch", "avg_launch_ms": round(avg_ms, 4),
+                     "fold_ms_per_launch": round(prof["fold_ms"] / max(1, prof["launches"]), 4)},
+    }
     print(json.dumps(out), flush=True)
     return 0
 

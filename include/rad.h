@@ -153,9 +153,6 @@ typedef struct rad_tile {
 int rad_get_tile(const rad_grid* g, rad_tile* t);
 int rad_set_tile(rad_grid* g, const rad_tile* t);
 
-/* Library and device facts: compute-unit count of `device`, or a negative code. */
-int rad_device_cus(int32_t device);
-
 /* Kernel timing of one grid.  While enabled, every accumulate launch and every fold
  * launch of the grid is bracketed by HIP events recorded on the launch's own stream.
  * rad_profile_read waits for the recorded events, returns the totals since the last read
@@ -168,6 +165,46 @@ typedef struct rad_profile_stats {
 } rad_profile_stats;
 int rad_profile_enable(rad_grid* g, int enable);
 int rad_profile_read(rad_grid* g, rad_profile_stats* out);
+
+/* ---- several grids in one persistent launch ------------------------------------ */
+
+/* One unit of batched work: n_steps consecutive steps (t_j = t0 + j*dt of the grid) of
+ * n_particles macro-particles each, accumulated into `grid` exactly as rad_push_steps
+ * would (arrays of n_steps * n_particles elements, step-major, device pointers). */
+typedef struct rad_batch_item {
+    rad_grid* grid;
+    double t0;
+    int32_t n_steps;
+    int64_t n_particles;
+    rad_particles p;
+} rad_batch_item;
+
+typedef struct rad_batcher rad_batcher;
+
+/* A batcher owns the device work plan and the partial-sum scratch of batched launches on
+ * `device`.  max_items bounds the items of one rad_batcher_push. */
+int rad_batcher_create(rad_batcher** out, int32_t device, int32_t max_items);
+int rad_batcher_destroy(rad_batcher* b);
+
+/* Accumulate every item into its grid with one persistent launch: the (item, tile,
+ * particle-chunk) iterations of all items are cut into equal contiguous ranges, one per
+ * workgroup, so bunches of very different sizes share the device evenly; then one fold
+ * launch adds the per-range partial tiles (fixed order, FP64) into each grid.  The result
+ * equals that of pushing each item on its own, up to FP32 rounding of the partial sums.
+ * Requirements: all grids on the batcher's device with the same precision mode and launch
+ * tile (w_per_lane, dir_per_wave, waves), all items of one particle dtype.  Several items
+ * may target the same grid.  Stream-ordered; the host blocks only to recycle a plan buffer
+ * used two calls earlier.  Calls on one batcher must be ordered on one stream. */
+int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int32_t n_items, void* stream);
+
+/* Kernel timing of a batcher's launches (same semantics as rad_profile_*). */
+int rad_batcher_profile_enable(rad_batcher* b, int enable);
+int rad_batcher_profile_read(rad_batcher* b, rad_profile_stats* out);
+
+/* Library and device facts: compute-unit count of `device`, or a negative code. */
+int rad_device_cus(int32_t device);
+
+
 
 #ifdef __cplusplus
 }

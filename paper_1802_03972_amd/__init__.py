@@ -179,6 +179,50 @@ class Grid:
         _lib.check(_lib.lib().rad_set_tile(self._h, ctypes.byref(t)))
 
 
+class Batcher:
+    """Accumulates many (grid, steps, particles) items with one persistent launch."""
+
+    def __init__(self, device: int = 0, max_items: int = 256):
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().rad_batcher_create(ctypes.byref(h), int(device), int(max_items)))
+        self._h = h
+        self.device = int(device)
+        self.max_items = int(max_items)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().rad_batcher_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, items, stream=None) -> None:
+        """items: iterable of (grid, t0, n_steps, particles) with particles a dict of CUDA
+        tensors holding n_steps * n_particles elements each (step-major)."""
+        items = list(items)
+        arr = (_lib.BatchItem * max(1, len(items)))()
+        keep = []
+        for k, (grid, t0, n_steps, parts) in enumerate(items):
+            p, n, ts = make_particles(parts, device=self.device)
+            keep.append(ts)
+            if n_steps <= 0 or n % n_steps:
+                raise ValueError("particle arrays must hold n_steps * n_particles elements")
+            arr[k] = _lib.BatchItem(grid.handle.value, float(t0), int(n_steps), n // n_steps, p)
+        _lib.check(_lib.lib().rad_batcher_push(self._h, arr, len(items), _stream_handle(stream, self.device)))
+
+    def profile(self, enable: bool = True) -> None:
+        _lib.check(_lib.lib().rad_batcher_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        st = _lib.ProfileStats()
+        _lib.check(_lib.lib().rad_batcher_profile_read(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.ProfileStats._fields_}
+
+
 def device_cus(device: int = 0) -> int:
     rc = _lib.lib().rad_device_cus(int(device))
     if rc < 0:

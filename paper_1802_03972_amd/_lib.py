@@ -50,6 +50,11 @@ class ProfileStats(ctypes.Structure):
                 ("accumulate_ms", ctypes.c_double), ("fold_ms", ctypes.c_double)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_void_p), ("t0", ctypes.c_double), ("n_steps", ctypes.c_int32),
+                ("n_particles", ctypes.c_int64), ("p", Particles)]
+
+
 # name -> (restype, argtypes); every symbol of include/rad.h and include/rad_debug.h
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -72,6 +77,11 @@ SIGNATURES = {
     "rad_device_cus": (ctypes.c_int, [ctypes.c_int32]),
     "rad_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rad_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ProfileStats)]),
+    "rad_batcher_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32]),
+    "rad_batcher_destroy": (ctypes.c_int, [_vp]),
+    "rad_batcher_push": (ctypes.c_int, [_vp, ctypes.POINTER(BatchItem), ctypes.c_int32, _vp]),
+    "rad_batcher_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rad_batcher_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ProfileStats)]),
     "rad_debug_trig_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
 }
 

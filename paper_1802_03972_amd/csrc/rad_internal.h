@@ -9,10 +9,10 @@ namespace rad {
 // Particles staged per workgroup chunk (one LDS round).
 constexpr int kChunk = 32;
 
-// Arguments of the accumulate kernel.  Pointers are device addresses.
-struct AccArgs {
+// One accumulation source: a particle range of one grid (one push, or one batch item).
+struct Job {
     const void* f[10];      // x, y, z, bx, by, bz, dbx, dby, dbz, w (element type = kernel InT)
-    int64_t i_begin;        // first particle index of this launch (into f[])
+    int64_t i_begin;        // first particle index (into f[])
     int64_t i_end;          // one past the last
     int64_t n_per_step;     // particles per time step (step of element i = i / n_per_step)
     double t0, dt;          // t_j = t0 + j * dt
@@ -20,12 +20,34 @@ struct AccArgs {
     const double* omega;    // [n_omega]
     const float2* gtab;     // [n_omega]: (g, 1 - g) of the shape
     double domega;
-    float* part;            // [splits][n_omega][n_dir][4] per-workgroup partial sums
-    int* err;               // sticky data-error flag
     int32_t n_dir, n_omega;
     int32_t tiles_d, tiles_w;
+    int* err;               // sticky data-error flag of the grid
+};
+
+// Arguments of the per-grid accumulate kernel: block b handles tile b % ntiles of split
+// b / ntiles, i.e. chunks [split * chunks_per_split, +chunks_per_split) of the job.
+struct AccArgs {
+    Job job;
+    float* part;            // [splits][n_omega][n_dir][4] per-workgroup partial sums
     int32_t splits;
     int64_t chunks_per_split;
+};
+
+// Batched launch: every workgroup walks its own list of segments; a segment is a chunk
+// range of one (item, tile) and owns one partial tile [TO][TD][4] in the segment buffer.
+struct BatchSeg {
+    int32_t item;
+    int32_t tile;
+    int64_t c_begin, c_end;
+};
+
+// Fold of one (grid, tile): sum of the listed segments' partial tiles into S.
+struct FoldJob {
+    double* S;              // grid accumulator, layout [n_omega][n_dir][4]
+    int32_t n_dir, n_omega;
+    int32_t td, tw;
+    int32_t list_begin, list_end;   // into the segment index list
 };
 
 struct LaunchShape {
@@ -39,13 +61,18 @@ inline int tile_omegas(const LaunchShape& s) { return s.waves * (64 / s.dir_per_
 inline size_t acc_lds_bytes(const LaunchShape& s)
 {
     const size_t td = tile_dirs(s), to = tile_omegas(s);
-    return kChunk * td * 16 + kChunk * td * 8 + 11 * kChunk * 8 + kChunk * to * 4;
+    return kChunk * td * 16 + kChunk * td * 8 + 11 * kChunk * 8 + kChunk * 8 + kChunk * to * 4;
 }
 
 // Launchers (stream-ordered, return hipError_t).
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
                              int n_blocks, hipStream_t st);
 hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st);
+hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,
+                                   float* seg_part, int dtype, int precision,
+                                   const LaunchShape& s, int n_blocks, hipStream_t st);
+hipError_t launch_fold_batch(const FoldJob* jobs, int n_jobs, const int32_t* seg_list,
+                             const float* seg_part, int td, int to, hipStream_t st);
 hipError_t launch_finalize(const double* S, double* I, int n_dir, int n_omega, double C,
                            hipStream_t st);
 hipError_t launch_cartesian(const double* S, const double* dirs9, double* out, int n_dir,

@@ -29,6 +29,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "rad_internal.h"
 
 namespace rad {
@@ -90,16 +93,16 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         const double b2 = bx * e2x + by * e2y + bz * e2z;
         const double q1 = dbx * e1x + dby * e1y + dbz * e1z;
         const double q2 = dbx * e2x + dby * e2y + dbz * e2z;
-        const double inv = 1.0 / (D * D);
-        const double a1 = -(b1 * nbd + q1 * D) * inv;
-        const double a2 = -(b2 * nbd + q2 * D) * inv;
+        // D^2 >= ~1e-13 is a normal FP32 number; A is kept in FP32, so an FP32 reciprocal
+        // (about 1 ulp) of the FP64 D^2 loses nothing that matters.
+        const float inv = __builtin_amdgcn_rcpf(static_cast<float>(D * D));
+        A1 = -static_cast<float>(b1 * nbd + q1 * D) * inv;
+        A2 = -static_cast<float>(b2 * nbd + q2 * D) * inv;
         const double tau = t - (nx * x + ny * y + nz * z) * kInvC;
         ph = tau * kInv2Pi;
         double rw = domega * ph;
         rw -= floor(rw);
-        sincos_rev_accurate(static_cast<float>(rw), wi, wr);
-        A1 = static_cast<float>(a1);
-        A2 = static_cast<float>(a2);
+        sincos_rev_fast(static_cast<float>(rw), wi, wr);
         bad = !(D > 0.0) || !(N >= 0.0) || !isfinite(N) || !isfinite(ph) || !isfinite(A1) ||
               !isfinite(A2);
     } else {
@@ -123,7 +126,7 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         const float phf = tau * (float)kInv2Pi;
         float rw = (float)domega * phf;
         rw -= floorf(rw);
-        sincos_rev_accurate(rw, wi, wr);
+        sincos_rev_fast(rw, wi, wr);
         ph = (double)phf;
         bad = !(D > 0.0f) || !(N >= 0.0) || !isfinite(N) || !isfinite(phf) || !isfinite(A1) ||
               !isfinite(A2);
@@ -133,8 +136,14 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
     ph_out = ph;
 }
 
+// Accumulate chunks [c_begin, c_end) of `j` into the tile (td, tw) and write the FP32
+// partial tile: element (omega o, direction d) of the tile goes to out[o * row + d] (as
+// (S1r, S1i, S2r, S2i)) when it lies inside the grid.  Every thread of the workgroup must
+// call this with the same arguments; LDS is reused chunk by chunk.
 template <typename InT, int PREC, int W, int DPW>
-__global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
+__device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, int64_t c_begin,
+                                                 int64_t c_end, float4* __restrict__ out, int row,
+                                                 float4* smem4)
 {
     constexpr int P = kChunk;
     constexpr int SUBS = 64 / DPW;
@@ -150,21 +159,15 @@ __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
     const int dl = lane % DPW;
     const int ob = wave * SUBS + lane / DPW;
 
-    const int ntiles = a.tiles_d * a.tiles_w;
-    const int tile = blockIdx.x % ntiles;
-    const int split = blockIdx.x / ntiles;
-    const int td = tile % a.tiles_d;
-    const int tw = tile / a.tiles_d;
-
-    extern __shared__ float4 smem4[];
     float4* geo = smem4;                                             // [P][TD]
     double* taus = reinterpret_cast<double*>(geo + P * TD);          // [P][TD]
     double* raw = taus + P * TD;                                     // [11][P]
-    float* ff = reinterpret_cast<float*>(raw + 11 * P);              // [P][TO]
+    float2* nw = reinterpret_cast<float2*>(raw + 11 * P);            // [P]: (N, N^2) in FP32
+    float* ff = reinterpret_cast<float*>(nw + P);                    // [P][TO]
 
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
-    const double om_first = a.omega[o_first < a.n_omega ? o_first : a.n_omega - 1];
+    const double om_first = j.omega[o_first < j.n_omega ? o_first : j.n_omega - 1];
 
     float s1r[W], s1i[W], s2r[W], s2i[W];
 #pragma unroll
@@ -172,46 +175,50 @@ __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
         s1r[k] = 0.f; s1i[k] = 0.f; s2r[k] = 0.f; s2i[k] = 0.f;
     }
 
-    const int64_t n_local = a.i_end - a.i_begin;
-    const int64_t nchunks = (n_local + P - 1) / P;
-    const int64_t c_begin = (int64_t)split * a.chunks_per_split;
-    int64_t c_end = c_begin + a.chunks_per_split;
-    if (c_end > nchunks) c_end = nchunks;
-
     for (int64_t c = c_begin; c < c_end; ++c) {
         // 1. stage the chunk (SoA, coalesced), widened to FP64, plus the step time.
         if (tid < P) {
-            const int64_t i = a.i_begin + c * P + tid;
-            const bool ok = i < a.i_end;
-            const int64_t ii = ok ? i : a.i_begin;
+            const int64_t i = j.i_begin + c * P + tid;
+            const bool ok = i < j.i_end;
+            const int64_t ii = ok ? i : j.i_begin;
 #pragma unroll
-            for (int f = 0; f < 10; ++f) raw[f * P + tid] = ok ? load_wide<InT>(a.f[f], ii) : 0.0;
-            const int64_t step = ii / a.n_per_step;
-            raw[10 * P + tid] = ok ? a.t0 + (double)step * a.dt : 0.0;
+            for (int f = 0; f < 10; ++f) raw[f * P + tid] = ok ? load_wide<InT>(j.f[f], ii) : 0.0;
+            // step = ii / n_per_step without a 64-bit integer division: the FP64 quotient of
+            // two integers below 2^53 is within one of the true one; correct it exactly.
+            int64_t step = 0;
+            if (j.i_end > j.n_per_step) {
+                step = (int64_t)floor((double)ii / (double)j.n_per_step);
+                if (step * j.n_per_step > ii) --step;
+                else if ((step + 1) * j.n_per_step <= ii) ++step;
+            }
+            raw[10 * P + tid] = ok ? j.t0 + (double)step * j.dt : 0.0;
+            const float N = ok ? (float)raw[9 * P + tid] : 0.f;
+            nw[tid] = make_float2(N, N * N);
         }
         __syncthreads();
         // 2. per (particle, direction) geometry.
         for (int i = tid; i < P * TD; i += nt) {
             const int m = i / TD;
             int dg = td * TD + (i % TD);
-            dg = dg < a.n_dir ? dg : a.n_dir - 1;
+            dg = dg < j.n_dir ? dg : j.n_dir - 1;
             float4 gv;
             double ph;
-            particle_direction_setup<PREC>(raw, m, a.dirs9 + 9 * dg, a.domega, gv, ph, a.err);
+            particle_direction_setup<PREC>(raw, m, j.dirs9 + 9 * dg, j.domega, gv, ph, j.err);
             geo[i] = gv;
             taus[i] = ph;
         }
-        // 3. per (particle, frequency) form-factor weight (Eq. 12), FP32.
-        for (int i = tid; i < P * TO; i += nt) {
-            const int m = i / TO;
-            const int og = tw * TO + (i % TO);
-            float F = 0.f;
-            if (og < a.n_omega) {
-                const float N = (float)raw[9 * P + m];
-                const float2 g = a.gtab[og];
-                F = __builtin_sqrtf(fmaf(N * N, g.x, N * g.y));
+        // 3. per (particle, frequency) form-factor weight F = sqrt(N^2 g + N (1 - g)) (Eq. 12),
+        //    FP32; frequencies outside the grid get F = 0 and contribute nothing.
+        for (int o = tid; o < TO; o += nt) {
+            const int og = tw * TO + o;
+            float2 g = make_float2(0.f, 0.f);
+            if (og < j.n_omega) g = j.gtab[og];
+            float* dst = ff + o;
+#pragma unroll 8
+            for (int m = 0; m < P; ++m, dst += TO) {
+                const float2 N = nw[m];
+                *dst = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
             }
-            ff[i] = F;
         }
         __syncthreads();
         // 4. hot loop.
@@ -253,16 +260,59 @@ __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
         __syncthreads();
     }
 
-    // 5. per-workgroup partial tile, layout [split][omega][dir][4] (coalesced over dir).
-    if (d < a.n_dir) {
-        float4* out = reinterpret_cast<float4*>(a.part);
+    // 5. partial tile (coalesced over directions).
+    if (d < j.n_dir) {
+        const int o_loc = ob * W;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            const int og = o_first + k;
-            if (og < a.n_omega)
-                out[((int64_t)split * a.n_omega + og) * a.n_dir + d] =
-                    make_float4(s1r[k], s1i[k], s2r[k], s2i[k]);
+            if (o_first + k < j.n_omega)
+                out[(int64_t)(o_loc + k) * row + dl] = make_float4(s1r[k], s1i[k], s2r[k], s2i[k]);
         }
+    }
+}
+
+template <typename InT, int PREC, int W, int DPW>
+__global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
+{
+    extern __shared__ float4 smem4[];
+    constexpr int TD = DPW;
+    const int TO = (blockDim.x >> 6) * (64 / DPW) * W;
+    const int ntiles = a.job.tiles_d * a.job.tiles_w;
+    const int tile = blockIdx.x % ntiles;
+    const int split = blockIdx.x / ntiles;
+    const int td = tile % a.job.tiles_d;
+    const int tw = tile / a.job.tiles_d;
+    const int64_t n_local = a.job.i_end - a.job.i_begin;
+    const int64_t nchunks = (n_local + kChunk - 1) / kChunk;
+    const int64_t c_begin = (int64_t)split * a.chunks_per_split;
+    int64_t c_end = c_begin + a.chunks_per_split;
+    if (c_end > nchunks) c_end = nchunks;
+    // partial layout [split][omega][dir]
+    float4* out = reinterpret_cast<float4*>(a.part) +
+                  ((int64_t)split * a.job.n_omega + (int64_t)tw * TO) * a.job.n_dir + td * TD;
+    accumulate_range<InT, PREC, W, DPW>(a.job, td, tw, c_begin, c_end, out, a.job.n_dir, smem4);
+}
+
+// Persistent batched accumulate: block r processes segments [wg_seg_begin[r], wg_seg_begin[r+1]),
+// each a chunk range of one (item, tile); segment s writes its partial tile [TO][TD] at
+// seg_part + s * TO * TD (float4 units).
+template <typename InT, int PREC, int W, int DPW>
+__global__ void __launch_bounds__(512) k_accumulate_batch(const Job* __restrict__ items,
+                                                          const int32_t* __restrict__ wg_seg_begin,
+                                                          const BatchSeg* __restrict__ segs,
+                                                          float* seg_part)
+{
+    extern __shared__ float4 smem4[];
+    constexpr int TD = DPW;
+    const int TO = (blockDim.x >> 6) * (64 / DPW) * W;
+    const int s0 = wg_seg_begin[blockIdx.x], s1 = wg_seg_begin[blockIdx.x + 1];
+    for (int s = s0; s < s1; ++s) {
+        const BatchSeg sg = segs[s];
+        const Job j = items[sg.item];
+        const int td = sg.tile % j.tiles_d;
+        const int tw = sg.tile / j.tiles_d;
+        float4* out = reinterpret_cast<float4*>(seg_part) + (int64_t)s * TO * TD;
+        accumulate_range<InT, PREC, W, DPW>(j, td, tw, sg.c_begin, sg.c_end, out, TD, smem4);
     }
 }
 
@@ -275,6 +325,32 @@ __global__ void k_fold(const float* __restrict__ part, double* __restrict__ S, i
     double s = 0.0;
     for (int k = 0; k < splits; ++k) s += (double)part[(int64_t)k * count + i];
     S[i] += s;
+}
+
+// Batched fold: for every (grid, tile) job and every in-grid point of the tile, add the
+// listed segments' partial values (in list order, FP64) into the grid's S.
+__global__ void k_fold_batch(const FoldJob* __restrict__ jobs, int n_jobs,
+                             const int32_t* __restrict__ seg_list, const float4* __restrict__ seg_part,
+                             int TD, int TO)
+{
+    const int64_t per_job = (int64_t)TD * TO;
+    const int64_t total = per_job * n_jobs;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int jb = (int)(idx / per_job);
+        const int e = (int)(idx % per_job);
+        const FoldJob fj = jobs[jb];
+        const int og = fj.tw * TO + e / TD;
+        const int dg = fj.td * TD + e % TD;
+        if (og >= fj.n_omega || dg >= fj.n_dir) continue;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int k = fj.list_begin; k < fj.list_end; ++k) {
+            const float4 v = seg_part[(int64_t)seg_list[k] * per_job + e];
+            a0 += (double)v.x; a1 += (double)v.y; a2 += (double)v.z; a3 += (double)v.w;
+        }
+        double* S = fj.S + ((int64_t)og * fj.n_dir + dg) * 4;
+        S[0] += a0; S[1] += a1; S[2] += a2; S[3] += a3;
+    }
 }
 
 // I[d][k] = C * (|S1|^2 + |S2|^2), S layout [omega][dir][4].
@@ -347,19 +423,61 @@ hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hi
     return hipGetLastError();
 }
 
-template <typename InT, int PREC>
-hipError_t launch_acc_p(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+struct BatchArgs {
+    const Job* items;
+    const int32_t* wg_seg_begin;
+    const BatchSeg* segs;
+    float* seg_part;
+};
+
+template <typename InT, int PREC, int W, int DPW>
+hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks, hipStream_t st)
 {
-    if (s.w_per_lane == 32) {
-        if (s.dir_per_wave == 64) return launch_acc_t<InT, PREC, 32, 64>(a, s, n_blocks, st);
-        if (s.dir_per_wave == 32) return launch_acc_t<InT, PREC, 32, 32>(a, s, n_blocks, st);
-        if (s.dir_per_wave == 16) return launch_acc_t<InT, PREC, 32, 16>(a, s, n_blocks, st);
-    } else if (s.w_per_lane == 16) {
-        if (s.dir_per_wave == 64) return launch_acc_t<InT, PREC, 16, 64>(a, s, n_blocks, st);
-        if (s.dir_per_wave == 32) return launch_acc_t<InT, PREC, 16, 32>(a, s, n_blocks, st);
-        if (s.dir_per_wave == 16) return launch_acc_t<InT, PREC, 16, 16>(a, s, n_blocks, st);
+    auto kern = k_accumulate_batch<InT, PREC, W, DPW>;
+    const size_t lds = acc_lds_bytes(s);
+    static size_t lds_allowed = 64 * 1024;
+    if (lds > lds_allowed) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_allowed = lds;
     }
+    hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, b.items, b.wg_seg_begin,
+                       b.segs, b.seg_part);
+    return hipGetLastError();
+}
+
+// Dispatch on the launch shape; Fn<W, DPW>::run(...) is the templated launcher.
+template <typename InT, int PREC, typename A>
+hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+{
+#define RAD_SHAPE_CASE(WW, DD)                                                        \
+    if (s.w_per_lane == WW && s.dir_per_wave == DD) {                                 \
+        if constexpr (std::is_same<A, AccArgs>::value)                                \
+            return launch_acc_t<InT, PREC, WW, DD>(a, s, n_blocks, st);               \
+        else                                                                          \
+            return launch_batch_t<InT, PREC, WW, DD>(a, s, n_blocks, st);             \
+    }
+    RAD_SHAPE_CASE(32, 64)
+    RAD_SHAPE_CASE(32, 32)
+    RAD_SHAPE_CASE(32, 16)
+    RAD_SHAPE_CASE(16, 64)
+    RAD_SHAPE_CASE(16, 32)
+    RAD_SHAPE_CASE(16, 16)
+#undef RAD_SHAPE_CASE
     return hipErrorInvalidValue;
+}
+
+template <typename A>
+hipError_t dispatch_all(const A& a, int dtype, int precision, const LaunchShape& s, int n_blocks,
+                        hipStream_t st)
+{
+    if (dtype == 0) {
+        return precision == 0 ? dispatch_shape<float, 0>(a, s, n_blocks, st)
+                              : dispatch_shape<float, 1>(a, s, n_blocks, st);
+    }
+    return precision == 0 ? dispatch_shape<double, 0>(a, s, n_blocks, st)
+                          : dispatch_shape<double, 1>(a, s, n_blocks, st);
 }
 
 }  // namespace
@@ -367,12 +485,26 @@ hipError_t launch_acc_p(const AccArgs& a, const LaunchShape& s, int n_blocks, hi
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
                              int n_blocks, hipStream_t st)
 {
-    if (dtype == 0) {
-        return precision == 0 ? launch_acc_p<float, 0>(a, s, n_blocks, st)
-                              : launch_acc_p<float, 1>(a, s, n_blocks, st);
-    }
-    return precision == 0 ? launch_acc_p<double, 0>(a, s, n_blocks, st)
-                          : launch_acc_p<double, 1>(a, s, n_blocks, st);
+    return dispatch_all(a, dtype, precision, s, n_blocks, st);
+}
+
+hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,
+                                   float* seg_part, int dtype, int precision,
+                                   const LaunchShape& s, int n_blocks, hipStream_t st)
+{
+    const BatchArgs b{items, wg_seg_begin, segs, seg_part};
+    return dispatch_all(b, dtype, precision, s, n_blocks, st);
+}
+
+hipError_t launch_fold_batch(const FoldJob* jobs, int n_jobs, const int32_t* seg_list,
+                             const float* seg_part, int td, int to, hipStream_t st)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    const int64_t total = (int64_t)n_jobs * td * to;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fold_batch, dim3(blocks), dim3(256), 0, st, jobs, n_jobs, seg_list,
+                       reinterpret_cast<const float4*>(seg_part), td, to);
+    return hipGetLastError();
 }
 
 hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st)

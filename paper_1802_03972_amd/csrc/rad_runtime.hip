@@ -115,8 +115,16 @@ struct rad_grid {
     double* d_omega = nullptr;
     float2* d_gtab = nullptr;
     double* d_S = nullptr;
-    float* d_part = nullptr;
+    // Two partial-sum buffers: the fold of push j (on fold_stream) overlaps the
+    // accumulate of push j+1 (on the caller's stream), which writes the other buffer.
+    float* d_part[2] = {nullptr, nullptr};
     int64_t part_splits = 0;
+    int part_next = 0;
+    hipStream_t fold_stream = nullptr;
+    hipEvent_t ev_acc_done[2] = {nullptr, nullptr};
+    hipEvent_t ev_fold_done[2] = {nullptr, nullptr};
+    bool fold_recorded[2] = {false, false};
+    int last_fold = -1;
     int* d_err = nullptr;
     double* d_out = nullptr;
     // kernel timing (rad_profile_*)
@@ -183,16 +191,20 @@ int ensure_partials(rad_grid* g)
 {
     const int64_t need = max_splits(g);
     if (need <= g->part_splits) return RAD_OK;
-    if (g->d_part) {
+    if (g->d_part[0] || g->d_part[1]) {
         RAD_HIP(hipDeviceSynchronize());
-        RAD_HIP(hipFree(g->d_part));
-        g->d_part = nullptr;
+        for (int b = 0; b < 2; ++b) {
+            if (g->d_part[b]) RAD_HIP(hipFree(g->d_part[b]));
+            g->d_part[b] = nullptr;
+        }
         g->part_splits = 0;
     }
     const size_t bytes = (size_t)need * g->n_omega * g->n_dir * 4 * sizeof(float);
-    if (hipMalloc(&g->d_part, bytes) != hipSuccess) {
-        g->d_part = nullptr;
-        return fail(RAD_ERR_OOM, "cannot allocate %zu B of partial sums", bytes);
+    for (int b = 0; b < 2; ++b) {
+        if (hipMalloc(&g->d_part[b], bytes) != hipSuccess) {
+            g->d_part[b] = nullptr;
+            return fail(RAD_ERR_OOM, "cannot allocate 2 x %zu B of partial sums", bytes);
+        }
     }
     g->part_splits = need;
     return RAD_OK;
@@ -227,7 +239,12 @@ void free_grid(rad_grid* g)
     if (g->d_omega) (void)hipFree(g->d_omega);
     if (g->d_gtab) (void)hipFree(g->d_gtab);
     if (g->d_S) (void)hipFree(g->d_S);
-    if (g->d_part) (void)hipFree(g->d_part);
+    for (int b = 0; b < 2; ++b) {
+        if (g->d_part[b]) (void)hipFree(g->d_part[b]);
+        if (g->ev_acc_done[b]) (void)hipEventDestroy(g->ev_acc_done[b]);
+        if (g->ev_fold_done[b]) (void)hipEventDestroy(g->ev_fold_done[b]);
+    }
+    if (g->fold_stream) (void)hipStreamDestroy(g->fold_stream);
     if (g->d_err) (void)hipFree(g->d_err);
     if (g->d_out) (void)hipFree(g->d_out);
     delete g;
@@ -245,6 +262,25 @@ int check_particles(const rad_particles* p)
     return RAD_OK;
 }
 
+void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0, int64_t n_per_step)
+{
+    j.f[0] = p->x; j.f[1] = p->y; j.f[2] = p->z;
+    j.f[3] = p->bx; j.f[4] = p->by; j.f[5] = p->bz;
+    j.f[6] = p->dbx; j.f[7] = p->dby; j.f[8] = p->dbz; j.f[9] = p->w;
+    j.n_per_step = n_per_step;
+    j.t0 = t0;
+    j.dt = g->dt;
+    j.dirs9 = g->d_dirs9;
+    j.omega = g->d_omega;
+    j.gtab = g->d_gtab;
+    j.domega = g->domega;
+    j.n_dir = g->n_dir;
+    j.n_omega = g->n_omega;
+    j.tiles_d = tiles_d(g);
+    j.tiles_w = tiles_w(g);
+    j.err = g->d_err;
+}
+
 // Accumulate particles [0, total) (step of element i is i / n_per_step, t = t0 + step*dt).
 int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const rad_particles* p,
                hipStream_t st)
@@ -256,32 +292,22 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
     const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;
     const int64_t per_launch_cap = (int64_t)g->part_splits * kMaxPerWorkgroup;
     AccArgs a{};
-    a.f[0] = p->x; a.f[1] = p->y; a.f[2] = p->z;
-    a.f[3] = p->bx; a.f[4] = p->by; a.f[5] = p->bz;
-    a.f[6] = p->dbx; a.f[7] = p->dby; a.f[8] = p->dbz; a.f[9] = p->w;
-    a.n_per_step = n_per_step;
-    a.t0 = t0;
-    a.dt = g->dt;
-    a.dirs9 = g->d_dirs9;
-    a.omega = g->d_omega;
-    a.gtab = g->d_gtab;
-    a.domega = g->domega;
-    a.part = g->d_part;
-    a.err = g->d_err;
-    a.n_dir = g->n_dir;
-    a.n_omega = g->n_omega;
-    a.tiles_d = td;
-    a.tiles_w = tw;
+    fill_job(a.job, g, p, t0, n_per_step);
     for (int64_t i0 = 0; i0 < total; i0 += per_launch_cap) {
         const int64_t i1 = std::min(total, i0 + per_launch_cap);
         const int64_t nchunks = (i1 - i0 + rad::kChunk - 1) / rad::kChunk;
         int64_t splits = std::min<int64_t>(g->part_splits, nchunks);
         const int64_t cps = (nchunks + splits - 1) / splits;
         splits = (nchunks + cps - 1) / cps;
-        a.i_begin = i0;
-        a.i_end = i1;
+        a.job.i_begin = i0;
+        a.job.i_end = i1;
         a.splits = (int32_t)splits;
         a.chunks_per_split = cps;
+        const int b = g->part_next;
+        g->part_next ^= 1;
+        a.part = g->d_part[b];
+        // the fold that last read this buffer must be done before it is overwritten
+        if (g->fold_recorded[b]) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[b], 0));
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
         if (g->profiling) {
             RAD_HIP(take_event(g, &e0));
@@ -295,14 +321,25 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
         }
         hipError_t e = rad::launch_accumulate(a, p->dtype, g->precision, ls, (int)(splits * nt), st);
         if (e != hipSuccess) return hip_fail(e, "accumulate launch");
-        if (g->profiling) {
-            RAD_HIP(hipEventRecord(e1, st));
-            RAD_HIP(hipEventRecord(e2, st));
-        }
-        e = rad::launch_fold(g->d_part, g->d_S, (int)splits, count, st);
+        if (g->profiling) RAD_HIP(hipEventRecord(e1, st));
+        RAD_HIP(hipEventRecord(g->ev_acc_done[b], st));
+        RAD_HIP(hipStreamWaitEvent(g->fold_stream, g->ev_acc_done[b], 0));
+        if (g->profiling) RAD_HIP(hipEventRecord(e2, g->fold_stream));
+        e = rad::launch_fold(g->d_part[b], g->d_S, (int)splits, count, g->fold_stream);
         if (e != hipSuccess) return hip_fail(e, "fold launch");
-        if (g->profiling) RAD_HIP(hipEventRecord(e3, st));
+        if (g->profiling) RAD_HIP(hipEventRecord(e3, g->fold_stream));
+        RAD_HIP(hipEventRecord(g->ev_fold_done[b], g->fold_stream));
+        g->fold_recorded[b] = true;
+        g->last_fold = b;
     }
+    return RAD_OK;
+}
+
+// Make `st` wait for every fold already enqueued (the fold stream is in order, so the
+// last one suffices).  Every call that touches the accumulator S on `st` does this first.
+int after_folds(rad_grid* g, hipStream_t st)
+{
+    if (g->last_fold >= 0) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[g->last_fold], 0));
     return RAD_OK;
 }
 
@@ -397,6 +434,14 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     }
     int rc = ensure_partials(g);
     if (rc) { free_grid(g); return rc; }
+    if (hipStreamCreateWithFlags(&g->fold_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_acc_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_acc_done[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_fold_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_fold_done[1], hipEventDisableTiming) != hipSuccess) {
+        free_grid(g);
+        return fail(RAD_ERR_DEVICE, "cannot create the grid's fold stream and events");
+    }
     hipError_t e;
     if ((e = hipMemcpy(g->d_dirs9, dirs9.data(), dirs9.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(g->d_omega, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -427,6 +472,7 @@ int rad_reset(rad_grid* g, void* stream)
     if (!g) return fail(RAD_ERR_INVALID_ARG, "grid is NULL");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
     hipError_t e = rad::launch_fill(g->d_S, (int64_t)g->n_dir * g->n_omega * 4, 0.0, st);
     if (e == hipSuccess) e = rad::launch_fill_int(g->d_err, 1, 0, st);
     if (e != hipSuccess) return hip_fail(e, "reset");
@@ -462,6 +508,7 @@ int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream)
 {
     if (!g || !I_dev) return fail(RAD_ERR_INVALID_ARG, "grid and output must be non-NULL");
     DeviceGuard dg(g->device);
+    if (int rc0 = after_folds(g, (hipStream_t)stream)) return rc0;
     hipError_t e = rad::launch_finalize(g->d_S, I_dev, g->n_dir, g->n_omega, g->C, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     return RAD_OK;
@@ -472,6 +519,7 @@ int rad_spectrum(rad_grid* g, double* I_host, void* stream)
     if (!g || !I_host) return fail(RAD_ERR_INVALID_ARG, "grid and output must be non-NULL");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
     hipError_t e = rad::launch_finalize(g->d_S, g->d_out, g->n_dir, g->n_omega, g->C, st);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
     int flag = 0;
@@ -489,6 +537,7 @@ int rad_spectrum_complex(rad_grid* g, double* S_host, void* stream)
     if (!g || !S_host) return fail(RAD_ERR_INVALID_ARG, "grid and output must be non-NULL");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
     hipError_t e = rad::launch_cartesian(g->d_S, g->d_dirs9, g->d_out, g->n_dir, g->n_omega, st);
     if (e != hipSuccess) return hip_fail(e, "cartesian launch");
     int flag = 0;
@@ -511,6 +560,7 @@ int rad_get_state(rad_grid* g, double* state_host, void* stream)
     if (!g || !state_host) return fail(RAD_ERR_INVALID_ARG, "grid and state must be non-NULL");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
     int flag = 0;
     int rc = read_err_flag(g, st, &flag);
     if (rc) return rc;
@@ -525,6 +575,7 @@ int rad_set_state(rad_grid* g, const double* state_host, void* stream)
     if (!g || !state_host) return fail(RAD_ERR_INVALID_ARG, "grid and state must be non-NULL");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
     RAD_HIP(hipMemcpyAsync(g->d_S, state_host, rad_state_size(g) * sizeof(double), hipMemcpyHostToDevice, st));
     hipError_t e = rad::launch_fill_int(g->d_err, 1, 0, st);
     if (e != hipSuccess) return hip_fail(e, "set_state");
@@ -595,6 +646,351 @@ extern "C" int rad_profile_read(rad_grid* g, rad_profile_stats* out)
     s.updates = g->prof_updates;
     g->prof_updates = 0;
     release_events(g);
+    *out = s;
+    return RAD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched launches over several grids.
+// ---------------------------------------------------------------------------------------
+#include <map>
+#include <utility>
+
+struct rad_batcher {
+    int device = 0;
+    int max_items = 0;
+    int cus = 0;
+    // Two plan buffers (pinned host + device); a plan buffer is rewritten only after the
+    // launch that read it two pushes earlier has finished (event `done`).
+    struct Slot {
+        unsigned char* host = nullptr;
+        unsigned char* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t done = nullptr;
+        bool used = false;
+    } slot[2];
+    int next = 0;
+    float* seg_part = nullptr;
+    size_t seg_part_floats = 0;
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_acc, ev_fold;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t prof_updates = 0;
+};
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hipError_t batch_event(rad_batcher* b, hipEvent_t* ev)
+{
+    if (!b->ev_pool.empty()) {
+        *ev = b->ev_pool.back();
+        b->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(ev);
+}
+
+void batch_release_events(rad_batcher* b)
+{
+    for (auto& e : b->ev_acc) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
+    for (auto& e : b->ev_fold) { b->ev_pool.push_back(e.first); b->ev_pool.push_back(e.second); }
+    b->ev_acc.clear();
+    b->ev_fold.clear();
+}
+
+void free_batcher(rad_batcher* b)
+{
+    if (!b) return;
+    DeviceGuard dg(b->device);
+    for (auto& s : b->slot) {
+        if (s.done) (void)hipEventSynchronize(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    if (b->seg_part) (void)hipFree(b->seg_part);
+    batch_release_events(b);
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    delete b;
+}
+
+struct ItemInfo {
+    rad::Job job;
+    int64_t chunks = 0;
+    int64_t iters = 0;     // tiles * chunks
+    int64_t iter_begin = 0;
+    rad_grid* grid = nullptr;
+};
+
+// One launch's plan over the global iteration range [L0, L1).
+struct LaunchPlan {
+    std::vector<int32_t> wg_seg_begin;
+    std::vector<rad::BatchSeg> segs;
+    std::vector<rad::FoldJob> jobs;
+    std::vector<int32_t> seg_list;
+};
+
+void build_plan(const std::vector<ItemInfo>& items, int64_t L0, int64_t L1, int R, LaunchPlan& pl)
+{
+    pl = LaunchPlan{};
+    const int64_t I = L1 - L0;
+    size_t it = 0;
+    while (it < items.size() && items[it].iter_begin + items[it].iters <= L0) ++it;
+    for (int r = 0; r < R; ++r) {
+        pl.wg_seg_begin.push_back((int32_t)pl.segs.size());
+        int64_t pos = L0 + I * r / R;
+        const int64_t end = L0 + I * (r + 1) / R;
+        while (pos < end) {
+            while (items[it].iter_begin + items[it].iters <= pos) ++it;
+            const ItemInfo& in = items[it];
+            const int64_t local = pos - in.iter_begin;
+            const int64_t tile = local / in.chunks;
+            const int64_t c0 = local % in.chunks;
+            const int64_t seg_end = std::min(end, in.iter_begin + (tile + 1) * in.chunks);
+            pl.segs.push_back(rad::BatchSeg{(int32_t)it, (int32_t)tile, c0, c0 + (seg_end - pos)});
+            pos = seg_end;
+        }
+    }
+    pl.wg_seg_begin.push_back((int32_t)pl.segs.size());
+    // fold jobs keyed by (grid, tile), segments listed in segment order
+    std::map<std::pair<const rad_grid*, int>, std::vector<int32_t>> groups;
+    std::vector<std::pair<const rad_grid*, int>> order;
+    for (size_t sidx = 0; sidx < pl.segs.size(); ++sidx) {
+        const auto& sg = pl.segs[sidx];
+        auto key = std::make_pair((const rad_grid*)items[sg.item].grid, (int)sg.tile);
+        auto f = groups.find(key);
+        if (f == groups.end()) {
+            order.push_back(key);
+            groups[key].push_back((int32_t)sidx);
+        } else {
+            f->second.push_back((int32_t)sidx);
+        }
+    }
+    for (const auto& key : order) {
+        const rad_grid* g = key.first;
+        const int tdn = tiles_d(g);
+        rad::FoldJob fj{};
+        fj.S = g->d_S;
+        fj.n_dir = g->n_dir;
+        fj.n_omega = g->n_omega;
+        fj.td = key.second % tdn;
+        fj.tw = key.second / tdn;
+        fj.list_begin = (int32_t)pl.seg_list.size();
+        for (int32_t sidx : groups[key]) pl.seg_list.push_back(sidx);
+        fj.list_end = (int32_t)pl.seg_list.size();
+        pl.jobs.push_back(fj);
+    }
+}
+
+}  // namespace
+
+extern "C" int rad_batcher_create(rad_batcher** out, int32_t device, int32_t max_items)
+{
+    if (!out) return fail(RAD_ERR_INVALID_ARG, "out is NULL");
+    if (max_items < 1 || max_items > (1 << 20)) return fail(RAD_ERR_INVALID_ARG, "max_items must be in 1..2^20");
+    const int cus = rad_device_cus(device);
+    if (cus < 0) return cus;
+    rad_batcher* b = new rad_batcher;
+    b->device = device;
+    b->max_items = max_items;
+    b->cus = cus;
+    DeviceGuard dg(device);
+    for (auto& s : b->slot) {
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            free_batcher(b);
+            return fail(RAD_ERR_DEVICE, "cannot create batcher events");
+        }
+    }
+    *out = b;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_destroy(rad_batcher* b)
+{
+    if (!b) return RAD_OK;
+    {
+        DeviceGuard dg(b->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_batcher(b);
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int32_t n_items, void* stream)
+{
+    if (!b) return fail(RAD_ERR_INVALID_ARG, "batcher is NULL");
+    if (n_items < 0 || n_items > b->max_items)
+        return fail(RAD_ERR_INVALID_ARG, "n_items %d outside 0..%d", n_items, b->max_items);
+    if (n_items > 0 && !items) return fail(RAD_ERR_INVALID_ARG, "items is NULL");
+    // validation
+    std::vector<ItemInfo> info;
+    const rad_grid* g0 = nullptr;
+    int dtype = -1;
+    for (int32_t i = 0; i < n_items; ++i) {
+        const rad_batch_item& itm = items[i];
+        if (!itm.grid) return fail(RAD_ERR_INVALID_ARG, "item %d has no grid", i);
+        if (itm.n_steps < 0 || itm.n_particles < 0) return fail(RAD_ERR_INVALID_ARG, "item %d has a negative size", i);
+        if (!std::isfinite(itm.t0)) return fail(RAD_ERR_INVALID_ARG, "item %d: t0 is not finite", i);
+        if (itm.grid->device != b->device)
+            return fail(RAD_ERR_INVALID_ARG, "item %d: grid on device %d, batcher on %d", i, itm.grid->device, b->device);
+        if (itm.n_steps == 0 || itm.n_particles == 0) continue;
+        int rc = check_particles(&itm.p);
+        if (rc) return rc;
+        if (!g0) {
+            g0 = itm.grid;
+            dtype = itm.p.dtype;
+        }
+        if (itm.p.dtype != dtype) return fail(RAD_ERR_INVALID_ARG, "item %d: particle dtype differs within the batch", i);
+        if (itm.grid->precision != g0->precision) return fail(RAD_ERR_INVALID_ARG, "item %d: precision mode differs", i);
+        const rad_tile& t = itm.grid->tile;
+        if (t.w_per_lane != g0->tile.w_per_lane || t.dir_per_wave != g0->tile.dir_per_wave || t.waves != g0->tile.waves)
+            return fail(RAD_ERR_INVALID_ARG, "item %d: launch tile differs from the first item's grid", i);
+        ItemInfo in;
+        fill_job(in.job, itm.grid, &itm.p, itm.t0, itm.n_particles);
+        in.job.i_begin = 0;
+        in.job.i_end = (int64_t)itm.n_steps * itm.n_particles;
+        in.chunks = (in.job.i_end + rad::kChunk - 1) / rad::kChunk;
+        in.iters = in.chunks * (int64_t)tiles_d(itm.grid) * tiles_w(itm.grid);
+        in.grid = itm.grid;
+        info.push_back(in);
+    }
+    if (info.empty()) return RAD_OK;
+    DeviceGuard dg(b->device);
+    hipStream_t st = (hipStream_t)stream;
+    // earlier single-grid folds of these grids must land before the batch fold
+    {
+        std::vector<rad_grid*> seen;
+        for (const auto& in : info) {
+            if (std::find(seen.begin(), seen.end(), in.grid) != seen.end()) continue;
+            seen.push_back(in.grid);
+            if (int rc = after_folds(in.grid, st)) return rc;
+        }
+    }
+    int64_t I = 0;
+    for (auto& in : info) {
+        in.iter_begin = I;
+        I += in.iters;
+    }
+    const LaunchShape ls = shape_of(g0->tile);
+    const int TD = rad::tile_dirs(ls), TO = rad::tile_omegas(ls);
+    const int R_target = std::max(1, b->cus * g0->tile.wg_per_cu);
+    const int64_t per_launch = (int64_t)R_target * (kMaxPerWorkgroup / rad::kChunk);
+    for (int64_t L0 = 0; L0 < I; L0 += per_launch) {
+        const int64_t L1 = std::min(I, L0 + per_launch);
+        const int R = (int)std::min<int64_t>(R_target, L1 - L0);
+        LaunchPlan pl;
+        build_plan(info, L0, L1, R, pl);
+        // plan bytes: items | wg_seg_begin | segs | jobs | seg_list
+        const size_t o_items = 0;
+        const size_t o_wsb = align_up(o_items + info.size() * sizeof(rad::Job), 16);
+        const size_t o_segs = align_up(o_wsb + pl.wg_seg_begin.size() * sizeof(int32_t), 16);
+        const size_t o_jobs = align_up(o_segs + pl.segs.size() * sizeof(rad::BatchSeg), 16);
+        const size_t o_list = align_up(o_jobs + pl.jobs.size() * sizeof(rad::FoldJob), 16);
+        const size_t bytes = align_up(o_list + pl.seg_list.size() * sizeof(int32_t), 16);
+        auto& sl = b->slot[b->next];
+        b->next ^= 1;
+        if (sl.used) RAD_HIP(hipEventSynchronize(sl.done));
+        if (bytes > sl.cap) {
+            if (sl.host) RAD_HIP(hipHostFree(sl.host));
+            if (sl.dev) RAD_HIP(hipFree(sl.dev));
+            sl.host = nullptr;
+            sl.dev = nullptr;
+            sl.cap = 0;
+            const size_t cap = std::max<size_t>(bytes * 2, 64 * 1024);
+            if (hipHostMalloc((void**)&sl.host, cap, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc((void**)&sl.dev, cap) != hipSuccess)
+                return fail(RAD_ERR_OOM, "cannot allocate a %zu B batch plan", cap);
+            sl.cap = cap;
+        }
+        for (size_t i = 0; i < info.size(); ++i) std::memcpy(sl.host + o_items + i * sizeof(rad::Job), &info[i].job, sizeof(rad::Job));
+        std::memcpy(sl.host + o_wsb, pl.wg_seg_begin.data(), pl.wg_seg_begin.size() * sizeof(int32_t));
+        std::memcpy(sl.host + o_segs, pl.segs.data(), pl.segs.size() * sizeof(rad::BatchSeg));
+        std::memcpy(sl.host + o_jobs, pl.jobs.data(), pl.jobs.size() * sizeof(rad::FoldJob));
+        std::memcpy(sl.host + o_list, pl.seg_list.data(), pl.seg_list.size() * sizeof(int32_t));
+        // segment scratch
+        const size_t need = pl.segs.size() * (size_t)TD * TO * 4;
+        if (need > b->seg_part_floats) {
+            if (b->seg_part) {
+                RAD_HIP(hipDeviceSynchronize());
+                RAD_HIP(hipFree(b->seg_part));
+                b->seg_part = nullptr;
+                b->seg_part_floats = 0;
+            }
+            const size_t alloc = need + need / 4;
+            if (hipMalloc((void**)&b->seg_part, alloc * sizeof(float)) != hipSuccess)
+                return fail(RAD_ERR_OOM, "cannot allocate %zu B of batch partial sums", alloc * sizeof(float));
+            b->seg_part_floats = alloc;
+        }
+        RAD_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st));
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+        if (b->profiling) {
+            RAD_HIP(batch_event(b, &e0));
+            RAD_HIP(batch_event(b, &e1));
+            RAD_HIP(batch_event(b, &e2));
+            RAD_HIP(batch_event(b, &e3));
+            b->ev_acc.emplace_back(e0, e1);
+            b->ev_fold.emplace_back(e2, e3);
+            for (const auto& sg : pl.segs) {
+                const ItemInfo& in = info[sg.item];
+                const int64_t lo = sg.c_begin * rad::kChunk;
+                const int64_t hi = std::min(in.job.i_end, sg.c_end * rad::kChunk);
+                const int td = sg.tile % in.job.tiles_d, tw = sg.tile / in.job.tiles_d;
+                const int64_t nd = std::min(TD, in.job.n_dir - td * TD);
+                const int64_t no = std::min(TO, in.job.n_omega - tw * TO);
+                b->prof_updates += (hi - lo) * nd * no;   // in-grid terms only
+            }
+            RAD_HIP(hipEventRecord(e0, st));
+        }
+        hipError_t e = rad::launch_accumulate_batch(
+            reinterpret_cast<const rad::Job*>(sl.dev + o_items), reinterpret_cast<const int32_t*>(sl.dev + o_wsb),
+            reinterpret_cast<const rad::BatchSeg*>(sl.dev + o_segs), b->seg_part, dtype, g0->precision, ls, R, st);
+        if (e != hipSuccess) return hip_fail(e, "batch accumulate launch");
+        if (b->profiling) {
+            RAD_HIP(hipEventRecord(e1, st));
+            RAD_HIP(hipEventRecord(e2, st));
+        }
+        e = rad::launch_fold_batch(reinterpret_cast<const rad::FoldJob*>(sl.dev + o_jobs), (int)pl.jobs.size(),
+                                   reinterpret_cast<const int32_t*>(sl.dev + o_list), b->seg_part, TD, TO, st);
+        if (e != hipSuccess) return hip_fail(e, "batch fold launch");
+        if (b->profiling) RAD_HIP(hipEventRecord(e3, st));
+        RAD_HIP(hipEventRecord(sl.done, st));
+        sl.used = true;
+    }
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_profile_enable(rad_batcher* b, int enable)
+{
+    if (!b) return fail(RAD_ERR_INVALID_ARG, "batcher is NULL");
+    batch_release_events(b);
+    b->prof_updates = 0;
+    b->profiling = enable != 0;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_profile_read(rad_batcher* b, rad_profile_stats* out)
+{
+    if (!b || !out) return fail(RAD_ERR_INVALID_ARG, "batcher and stats must be non-NULL");
+    DeviceGuard dg(b->device);
+    rad_profile_stats s{};
+    for (auto& e : b->ev_acc) {
+        RAD_HIP(hipEventSynchronize(e.second));
+        float ms = 0.f;
+        RAD_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        s.accumulate_ms += ms;
+        s.launches += 1;
+    }
+    for (auto& e : b->ev_fold) {
+        RAD_HIP(hipEventSynchronize(e.second));
+        float ms = 0.f;
+        RAD_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+        s.fold_ms += ms;
+    }
+    s.updates = b->prof_updates;
+    b->prof_updates = 0;
+    batch_release_events(b);
     *out = s;
     return RAD_OK;
 }

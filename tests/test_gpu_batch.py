@@ -1,0 +1,118 @@
+"""Batched persistent launch over several grids (uneven bunches), through the C ABI.
+
+Each grid's spectrum from one batched push must equal the oracle (1e-4 of the peak), the
+per-grid push of the same particles (FP32 rounding only), and the same bunch pushed alone
+(alone vs in the mix).  Repeating the same mix is bitwise reproducible.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import SINGLE, batched_uneven, flatten
+from tests.helpers import e_inf, to_device
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rad():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1802_03972_amd as rad
+    rad._lib.lib()
+    return rad
+
+
+def bunches(counts, steps=2, **kw):
+    out = []
+    for i, n in enumerate(counts):
+        w = SINGLE.scaled(n_particles=int(n), n_steps=steps, nx_dir=8, ny_dir=8, n_omega=256,
+                          seed=100 + i, **kw)
+        out.append((w, w.steps()))
+    return out
+
+
+def grid_for(rad, w):
+    return rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
+                    shape_len=w.shape_len, dt=w.dt)
+
+
+def test_batch_matches_oracle_and_single_pushes(rad):
+    bs = bunches([37, 3000, 777, 12000, 5, 200])
+    grids = [grid_for(rad, w) for w, _ in bs]
+    devs = [to_device(st, w.in_dtype) for w, st in bs]
+    b = rad.Batcher(max_items=16)
+    b.push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(grids, bs, devs)])
+    for g, (w, st), d in zip(grids, bs, devs):
+        I = g.spectrum()
+        if w.n_particles <= 3000:
+            Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape,
+                                   w.shape_len, w.dt)
+            err = e_inf(I, Iref)
+            print(f"batch n={w.n_particles}: e_inf vs oracle {err:.3e}")
+            assert err <= TOL
+        g1 = grid_for(rad, w)
+        g1.push_steps(w.t0, w.n_steps, d)
+        assert e_inf(I, g1.spectrum()) <= 1e-6
+
+
+def test_alone_vs_in_the_mix(rad):
+    bs = bunches([500, 9000, 64, 4000], steps=3)
+    devs = [to_device(st, w.in_dtype) for w, st in bs]
+    b = rad.Batcher(max_items=8)
+    mixed = [grid_for(rad, w) for w, _ in bs]
+    b.push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(mixed, bs, devs)])
+    again = [grid_for(rad, w) for w, _ in bs]
+    b.push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(again, bs, devs)])
+    for k, ((w, _), d) in enumerate(zip(bs, devs)):
+        alone = grid_for(rad, w)
+        b.push([(alone, w.t0, w.n_steps, d)])
+        Im = mixed[k].spectrum()
+        assert e_inf(Im, alone.spectrum()) <= 1e-6
+        assert np.array_equal(Im, again[k].spectrum())
+
+
+def test_several_items_on_one_grid(rad):
+    (w, st), = bunches([2500], steps=4)
+    d = to_device(st, w.in_dtype)
+    n = w.n_particles
+    g_all = grid_for(rad, w)
+    g_all.push_steps(w.t0, 4, d)
+    g_split = grid_for(rad, w)
+    first = {k: v[:2 * n] for k, v in d.items()}
+    second = {k: v[2 * n:] for k, v in d.items()}
+    rad.Batcher().push([(g_split, w.t0, 2, first), (g_split, w.t0 + 2 * w.dt, 2, second)])
+    assert e_inf(g_split.spectrum(), g_all.spectrum()) <= 1e-6
+
+
+def test_batch_rejects_mismatched_tiles(rad):
+    bs = bunches([100, 100], steps=1)
+    grids = [grid_for(rad, w) for w, _ in bs]
+    grids[1].set_tile(w_per_lane=16)
+    devs = [to_device(st, w.in_dtype) for w, st in bs]
+    with pytest.raises(rad.RadError) as ei:
+        rad.Batcher().push([(g, w.t0, 1, d) for g, (w, _), d in zip(grids, bs, devs)])
+    assert ei.value.code == rad.RAD_ERR_INVALID_ARG
+
+
+def test_batched_uneven_full_counts_one_step(rad):
+    """The 12-bunch workload at its real particle counts (one step), two bunches sampled
+    against the oracle on every 16th frequency."""
+    mb = batched_uneven()
+    ws = [w.scaled(n_steps=1) for w in mb.bunches()]
+    sts = [w.steps() for w in ws]
+    grids = [grid_for(rad, w) for w in ws]
+    devs = [to_device(st, w.in_dtype) for w, st in zip(ws, sts)]
+    rad.Batcher(max_items=16).push([(g, w.t0, 1, d) for g, w, d in zip(grids, ws, devs)])
+    order = np.argsort(mb.counts)
+    sel = np.arange(0, 256, 16)
+    for k in (order[0], order[len(order) // 2]):
+        w = ws[k]
+        I = grids[k].spectrum()[:, sel]
+        Iref = oracle.spectrum(flatten(sts[k], w.times()), w.directions(), w.omegas()[sel], w.shape,
+                               w.shape_len, w.dt)
+        err = e_inf(I, Iref)
+        print(f"batched_uneven bunch {k} (n={w.n_particles}): e_inf {err:.3e}")
+        assert err <= TOL
