@@ -201,6 +201,68 @@ int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int32_t n_item
 int rad_batcher_profile_enable(rad_batcher* b, int enable);
 int rad_batcher_profile_read(rad_batcher* b, rad_profile_stats* out);
 
+/* ---- serving loop: continuous batching of per-step chunks of many bunches -------- */
+
+typedef struct rad_server rad_server;
+
+typedef struct rad_server_config {
+    int32_t device;
+    size_t hbm_budget;      /* bytes of device memory for admitted chunks (>= 1 MiB)      */
+    int32_t max_batch;      /* chunks per batched launch (>= 1)                            */
+    int32_t max_inflight;   /* batched launches queued on the device at once (1 or 2;
+                               larger values are treated as 2)                             */
+    int32_t max_admitted;   /* chunks admitted (copying or copied) but not yet launched    */
+    int64_t max_pending;    /* chunks submitted but not yet admitted; beyond it submit
+                               returns RAD_ERR_QUEUE_FULL                                  */
+    int32_t poll_us;        /* scheduler wake-up period when nothing moves [us] (>= 1)     */
+} rad_server_config;
+
+/* Per-chunk timeline on the server clock [s since creation] and the launch it rode in. */
+typedef struct rad_chunk_stats {
+    double t_submit, t_admit, t_launch, t_complete;
+    int32_t batch_size;
+    int32_t status;          /* RAD_OK or the first error the server met */
+} rad_chunk_stats;
+
+typedef struct rad_server_counters {
+    int64_t submitted, admitted, chunks_launched, batches, completed;
+    int64_t pending;           /* waiting for admission (backlog)       */
+    int64_t admitted_waiting;  /* admitted, not yet launched            */
+    int64_t inflight_batches;
+    size_t pool_used;          /* bytes of the HBM budget in use        */
+    double now;                /* server clock [s]                      */
+} rad_server_counters;
+
+/* Start a server with its own scheduler thread, copy and compute streams (default
+ * priority) and a device chunk pool of hbm_budget bytes on cfg->device. */
+int rad_server_create(rad_server** out, const rad_server_config* cfg);
+
+/* Queue one chunk: n particles of one time step t of `grid`, given in HOST memory (SoA,
+ * one dtype).  The host arrays must stay valid and unchanged until the chunk completes.
+ * Admission is in arrival order, when the chunk's device footprint (10 fields, 256-byte
+ * aligned) fits in the free part of the budget; the server then copies it, batches it with
+ * every other copied chunk (any bunch) into one batched persistent launch, and releases
+ * its bytes when the launch completes.  Never drops a chunk; a chunk larger than the whole
+ * budget is rejected (RAD_ERR_INVALID_ARG).  Chunks of one grid may be in flight together.
+ * While a server runs, other calls on its grids must wait for rad_server_drain. */
+int rad_server_submit(rad_server* s, rad_grid* grid, double t, int64_t n, const rad_particles* host_p,
+                      uint64_t* ticket);
+
+/* 1 and the chunk's stats if the chunk completed (the ticket is then retired), 0 if not
+ * yet, negative on error. */
+int rad_server_poll(rad_server* s, uint64_t ticket, rad_chunk_stats* st);
+
+/* Block until the chunk completes; 1 on success (ticket retired) or a negative code. */
+int rad_server_wait(rad_server* s, uint64_t ticket, rad_chunk_stats* st);
+
+/* Block until every submitted chunk has completed. */
+int rad_server_drain(rad_server* s);
+
+int rad_server_counters_read(rad_server* s, rad_server_counters* out);
+
+/* Drain, stop the scheduler thread and free the server (not its grids). */
+int rad_server_destroy(rad_server* s);
+
 /* Library and device facts: compute-unit count of `device`, or a negative code. */
 int rad_device_cus(int32_t device);
 

@@ -223,6 +223,88 @@ class Batcher:
         return {k: getattr(st, k) for k, _ in _lib.ProfileStats._fields_}
 
 
+class Server:
+    """Continuous-batching serving loop (scheduler thread in librad.so).
+
+    submit() takes one chunk (one time step of one bunch) as HOST arrays: a dict of numpy
+    arrays or CPU tensors (pinned memory lets the copies run asynchronously).  The arrays
+    are kept alive here until the chunk completes."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 1 << 30, max_batch: int = 64,
+                 max_inflight: int = 2, max_admitted: int = 256, max_pending: int = 1 << 20,
+                 poll_us: int = 20):
+        cfg = _lib.ServerConfig(int(device), int(hbm_budget), int(max_batch), int(max_inflight),
+                                int(max_admitted), int(max_pending), int(poll_us))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().rad_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self._h = h
+        self._keep = {}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().rad_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, grid: "Grid", t: float, host_fields: dict) -> int:
+        arrs = []
+        for k in FIELDS:
+            a = host_fields[k]
+            if hasattr(a, "is_cuda"):
+                if a.is_cuda or not a.is_contiguous():
+                    raise ValueError(f"field {k} must be a contiguous CPU tensor")
+                ptr, n, dt = a.data_ptr(), a.numel(), str(a.dtype).replace("torch.", "")
+            else:
+                a = np.ascontiguousarray(a)
+                ptr, n, dt = a.ctypes.data, a.size, str(a.dtype)
+            arrs.append((a, ptr, n, dt))
+        n, dt = arrs[0][2], arrs[0][3]
+        if any(x[2] != n or x[3] != dt for x in arrs) or dt not in ("float32", "float64"):
+            raise ValueError("all fields must share one length and dtype (float32 or float64)")
+        p = _lib.Particles(F32 if dt == "float32" else F64, *[x[1] for x in arrs])
+        tk = ctypes.c_uint64()
+        _lib.check(_lib.lib().rad_server_submit(self._h, grid.handle, float(t), int(n), ctypes.byref(p),
+                                                ctypes.byref(tk)))
+        self._keep[tk.value] = arrs
+        return tk.value
+
+    @staticmethod
+    def _stats(st) -> dict:
+        return {k: getattr(st, k) for k, _ in _lib.ChunkStats._fields_}
+
+    def poll(self, ticket: int):
+        st = _lib.ChunkStats()
+        rc = _lib.lib().rad_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(st))
+        if rc < 0:
+            _lib.check(rc)
+        if rc == 0:
+            return None
+        self._keep.pop(ticket, None)
+        return self._stats(st)
+
+    def wait(self, ticket: int) -> dict:
+        st = _lib.ChunkStats()
+        rc = _lib.lib().rad_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(st))
+        if rc < 0:
+            _lib.check(rc)
+        self._keep.pop(ticket, None)
+        return self._stats(st)
+
+    def drain(self) -> None:
+        _lib.check(_lib.lib().rad_server_drain(self._h))
+
+    def counters(self) -> dict:
+        c = _lib.ServerCounters()
+        _lib.check(_lib.lib().rad_server_counters_read(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in _lib.ServerCounters._fields_}
+
+
 def device_cus(device: int = 0) -> int:
     rc = _lib.lib().rad_device_cus(int(device))
     if rc < 0:

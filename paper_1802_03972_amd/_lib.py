@@ -55,6 +55,24 @@ class BatchItem(ctypes.Structure):
                 ("n_particles", ctypes.c_int64), ("p", Particles)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_admitted", ctypes.c_int32),
+                ("max_pending", ctypes.c_int64), ("poll_us", ctypes.c_int32)]
+
+
+class ChunkStats(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_complete", ctypes.c_double), ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("chunks_launched", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("completed", ctypes.c_int64), ("pending", ctypes.c_int64),
+                ("admitted_waiting", ctypes.c_int64), ("inflight_batches", ctypes.c_int64),
+                ("pool_used", ctypes.c_size_t), ("now", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); every symbol of include/rad.h and include/rad_debug.h
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -82,6 +100,14 @@ SIGNATURES = {
     "rad_batcher_push": (ctypes.c_int, [_vp, ctypes.POINTER(BatchItem), ctypes.c_int32, _vp]),
     "rad_batcher_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rad_batcher_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ProfileStats)]),
+    "rad_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ServerConfig)]),
+    "rad_server_submit": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(Particles),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "rad_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ChunkStats)]),
+    "rad_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ChunkStats)]),
+    "rad_server_drain": (ctypes.c_int, [_vp]),
+    "rad_server_counters_read": (ctypes.c_int, [_vp, ctypes.POINTER(ServerCounters)]),
+    "rad_server_destroy": (ctypes.c_int, [_vp]),
     "rad_debug_trig_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
 }
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librad.so")
-SOURCES = ["rad_kernels.hip", "rad_runtime.hip"]
+SOURCES = ["rad_kernels.hip", "rad_runtime.hip", "rad_server.hip"]
 ARCH = os.environ.get("RAD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

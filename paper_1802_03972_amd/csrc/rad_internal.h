@@ -64,6 +64,9 @@ inline size_t acc_lds_bytes(const LaunchShape& s)
     return kChunk * td * 16 + kChunk * td * 8 + 11 * kChunk * 8 + kChunk * 8 + kChunk * to * 4;
 }
 
+// Sets the calling thread's message returned by rad_last_error().
+void set_last_error(const char* msg);
+
 // Launchers (stream-ordered, return hipError_t).
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
                              int n_blocks, hipStream_t st);
