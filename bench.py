@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single_bunch_fp32",
                     choices=["single_bunch_fp32", "tiny_fp64", "batched_uneven", "serving"])
+    ap.add_argument("--time-steps", type=int, default=0, help="batched_uneven: override the 200 time steps")
+    ap.add_argument("--skip-per-bunch", action="store_true", help="batched_uneven: time only the batched launch")
     ap.add_argument("--chunks", type=int, default=4000, help="serving: chunks in the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate [chunks/s]")
     ap.add_argument("--distinct-steps", type=int, default=8,
@@ -60,6 +62,27 @@ def calibrate_copy(mib: int) -> int:
     print(json.dumps({"calibration": "copy", "bytes_read_per_dispatch": n * 4, "bytes_written_per_dispatch": n * 4,
                       "dispatches": 5}), flush=True)
     return 0
+
+
+def profiled_traffic(profile: str):
+    """HBM bytes per launch of the accumulate kernel from the committed rocprofv3 summary,
+    or None if the kernel source changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    src = os.path.join(ROOT, "paper_1802_03972_amd", "csrc", "rad_kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.strip()
+    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(msg: str) -> None:
@@ -149,7 +172,9 @@ def main() -> int:
     upd_per_launch = prof["updates"] / max(1, prof["launches"])
     achieved = upd_per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md") if w is SINGLE else None,
+                "traffic_source": "profiles/k_accumulate_single_bunch_fp32.md (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, bytes per launch)",
                 "kernel": "k_accumulate", "avg_launch_ms": round(avg_ms, 4),
                 "updates_per_launch": int(upd_per_launch), "flops_per_update": FLOPS_PER_UPDATE,
                 "fold_ms_per_launch": round(prof["fold_ms"] / max(1, prof["launches"]), 4)}
@@ -228,6 +253,8 @@ def bench_batched(args) -> int:
 
     mb = batched_uneven()
     ws = mb.bunches()
+    if args.time_steps:
+        ws = [w.scaled(n_steps=args.time_steps) for w in ws]
     n_steps = ws[0].n_steps
     kd = max(1, min(args.distinct_steps, n_steps))
     log(f"[bench] batched_uneven: counts {list(mb.counts)}, {n_steps} steps ({kd} distinct generated steps cycled)")
@@ -269,16 +296,19 @@ def bench_batched(args) -> int:
         return (time.perf_counter() - t0) / reps
 
     reps = max(1, args.steps)
-    t_pb = timed(per_bunch, reps)
-    log(f"[bench] per-bunch launches: {t_pb * 1e3:.1f} ms per {n_steps} steps ({updates / t_pb:.4e} updates/s)")
-    I_pb = [g.spectrum() for g in grids]
+    if args.skip_per_bunch:
+        t_pb, I_pb = float("nan"), None
+    else:
+        t_pb = timed(per_bunch, reps)
+        log(f"[bench] per-bunch launches: {t_pb * 1e3:.1f} ms per {n_steps} steps ({updates / t_pb:.4e} updates/s)")
+        I_pb = [g.spectrum() for g in grids]
     batcher.profile(True)
     t_b = timed(batched, reps)
     prof = batcher.profile_read()
     batcher.profile(False)
     log(f"[bench] batched persistent: {t_b * 1e3:.1f} ms per {n_steps} steps ({updates / t_b:.4e} updates/s)")
     I_b = [g.spectrum() for g in grids]
-    agree = max(float(np.max(np.abs(a - b)) / np.max(a)) for a, b in zip(I_pb, I_b))
+    agree = None if I_pb is None else max(float(np.max(np.abs(a - b)) / np.max(a)) for a, b in zip(I_pb, I_b))
     avg_ms = prof["accumulate_ms"] / max(1, prof["launches"])
     achieved = prof["updates"] / max(1, prof["launches"]) * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     out = {
