@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single_bunch_fp32",
-                    choices=["single_bunch_fp32", "tiny_fp64", "batched_uneven", "serving"])
+                    choices=["single_bunch_fp32", "tiny_fp64", "batched_uneven", "serving", "precision_stress"])
     ap.add_argument("--time-steps", type=int, default=0, help="batched_uneven: override the 200 time steps")
     ap.add_argument("--skip-per-bunch", action="store_true", help="batched_uneven: time only the batched launch")
     ap.add_argument("--chunks", type=int, default=4000, help="serving: chunks in the arrival trace")
@@ -110,6 +110,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "precision_stress":
+        return bench_precision(args)
 
     w = SINGLE if args.workload == "single_bunch_fp32" else TINY
     dev_id = 0
@@ -416,6 +418,110 @@ def bench_serving(args) -> int:
         "latency_ms": {"p50": full["p50_ms"], "p99": full["p99_ms"], "unit": "ms",
                        "what": "chunk arrival to completion"},
         "serving": full, "load_scaled": scaled,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def error_report(I, Iref) -> dict:
+    import numpy as np
+    peak = float(np.max(Iref))
+    diff = np.abs(I - Iref)
+    big = Iref >= 1e-2 * peak
+    col = np.maximum(np.max(Iref, axis=0), 1e-300)
+    return {"e_inf": float(np.max(diff) / peak),
+            "per_frequency_max": float(np.max(np.max(diff, axis=0) / col)),
+            "per_frequency_max_top_quarter": float(np.max((np.max(diff, axis=0) / col)[-max(1, Iref.shape[1] // 4):])),
+            "l2_rel": float(np.linalg.norm(I - Iref) / np.linalg.norm(Iref)),
+            "per_direction_max": float(max(np.max(diff[d]) / max(np.max(Iref[d]), 1e-300)
+                                           for d in range(Iref.shape[0]))),
+            "per_point_rel_max_bins_ge_1e-2_peak": float(np.max(diff[big] / Iref[big])) if big.any() else 0.0,
+            "abs_max": float(np.max(diff)), "peak": peak}
+
+
+def bench_precision(args) -> int:
+    """Precision stress: 16384 particles x 10000 steps from t0 = 1 ps, gamma ~ U(50, 1000),
+    8x8 x 1024 frequencies to 1e20 rad/s, FP64 input.  Both arithmetic modes (FP64 geometry
+    and phase with FP32 update; everything FP32) accumulate every step on the device; the
+    FP64 oracle (the CPU-baseline leg) evaluates 4 directions x 9 frequencies of the same
+    sum, and both device spectra are compared with it there.  Steps are generated, pushed
+    and handed to the oracle in groups of 100."""
+    import numpy as np
+    import torch
+
+    import paper_1802_03972_amd as rad
+    from workloads import PRECISION, SINGLE, flatten
+
+    w = PRECISION
+    n_steps = args.time_steps or w.n_steps
+    group = 100
+    bunch = w.bunch()
+    grids = {"fp64_phase": rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
+                                    shape_len=w.shape_len, dt=w.dt, precision=rad.PHASE_F64),
+             "all_fp32": rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
+                                  shape_len=w.shape_len, dt=w.dt, precision=rad.ALL_F32)}
+    for g in grids.values():
+        g.profile(True)
+    dsel = np.array([0, 9, 36, 63])
+    osel = np.unique(np.concatenate([np.arange(0, w.n_omega, 128), [w.n_omega - 1]]))
+    use_oracle = not args.no_cpu_baseline
+    S_ref = None
+    cpu_s = 0.0
+    if use_oracle:
+        import oracle
+        oracle.set_threads(len(os.sched_getaffinity(0)))
+    log(f"[bench] precision_stress: {w.n_particles} particles x {n_steps} steps from t0 = {w.t0:g} s")
+    for j0 in range(0, n_steps, group):
+        j1 = min(n_steps, j0 + group)
+        st = w.steps(j0, j1, bunch=bunch)
+        dev = {k: torch.as_tensor(np.ascontiguousarray(st[k]).reshape(-1)).to("cuda:0") for k in rad.FIELDS}
+        t0 = float(w.times(j0, j0 + 1)[0])
+        for g in grids.values():
+            g.push_steps(t0, j1 - j0, dev)
+        if use_oracle:   # cpu_baseline leg: the FP64 oracle on the direction x frequency subset
+            tc = time.perf_counter()
+            S = oracle.spectrum_complex(flatten(st, w.times(j0, j1)), w.directions()[dsel], w.omegas()[osel],
+                                        w.shape, w.shape_len)
+            cpu_s += time.perf_counter() - tc
+            S_ref = S if S_ref is None else S_ref + S
+        torch.cuda.synchronize()
+        if j0 % 1000 == 0:
+            log(f"[bench] steps {j1}/{n_steps}")
+    out_modes = {}
+    for name, g in grids.items():
+        prof = g.profile_read()
+        out_modes[name] = {"updates_per_s_kernel": prof["updates"] / (prof["accumulate_ms"] * 1e-3),
+                           "accumulate_ms": prof["accumulate_ms"]}
+    cpu = None
+    if use_oracle:
+        Iref = oracle.prefactor(w.dt) * np.sum(np.abs(S_ref) ** 2, axis=-1)
+        for name, g in grids.items():
+            out_modes[name]["errors_vs_oracle"] = error_report(g.spectrum()[np.ix_(dsel, osel)], Iref)
+            log(f"[bench] {name}: {out_modes[name]}")
+        upd = w.n_particles * n_steps * len(dsel) * len(osel)
+        cpu = {"value": upd / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"all {n_steps} steps x {w.n_particles} particles, directions {dsel.tolist()}, "
+                         f"frequency indices {osel.tolist()} ({upd:.3e} updates, {cpu_s:.1f} s)"}
+        # input rounding of the FP32-input single-bunch workload: oracle on the FP64 trajectory
+        # vs oracle on the FP32-rounded one (4 steps, every 16th frequency)
+        ws = SINGLE.scaled(n_steps=4)
+        b2 = ws.bunch()
+        from workloads import stack_steps
+        exact = stack_steps(b2, ws.times())
+        rounded = {k: v.astype(np.float32).astype(np.float64) for k, v in exact.items()}
+        om = ws.omegas()[::16]
+        I_exact = oracle.spectrum(flatten(exact, ws.times()), ws.directions(), om, ws.shape, ws.shape_len, ws.dt)
+        I_round = oracle.spectrum(flatten(rounded, ws.times()), ws.directions(), om, ws.shape, ws.shape_len, ws.dt)
+        input_rounding = error_report(I_round, I_exact)
+    out = {
+        "metric": "particle*direction*frequency updates/s (vs FP32 peak); p50/p99 step latency",
+        "value": out_modes["fp64_phase"]["updates_per_s_kernel"], "unit": "updates/s", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0, "ms_per_step": out_modes["fp64_phase"]["accumulate_ms"] / n_steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "precision_stress", "particles": w.n_particles, "time_steps": n_steps, "t0": w.t0,
+                   "directions": w.n_dir, "frequencies": w.n_omega, "omega_max": w.omega_max, "input_dtype": "f64"},
+        "modes": out_modes, "cpu_baseline": cpu,
+        "input_rounding_single_bunch_fp32": input_rounding if use_oracle else None,
     }
     print(json.dumps(out), flush=True)
     return 0

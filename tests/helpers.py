@@ -28,3 +28,21 @@ def step_slice(dev: dict, j: int, n: int) -> dict:
 
 def oracle_samples(steps: dict, times) -> dict:
     return flatten(steps, times)
+
+
+def error_report(I, Iref) -> dict:
+    """e_inf (gate), L2 relative, per-direction peak-normalised max, and per-point relative
+    error on bins holding at least 1e-2 of the peak."""
+    I = np.asarray(I, np.float64)
+    Iref = np.asarray(Iref, np.float64)
+    peak = float(np.max(Iref))
+    diff = np.abs(I - Iref)
+    per_dir = [float(np.max(diff[d]) / max(np.max(Iref[d]), 1e-300)) for d in range(Iref.shape[0])]
+    big = Iref >= 1e-2 * peak
+    col = np.maximum(np.max(Iref, axis=0), 1e-300)
+    return {"e_inf": float(np.max(diff) / peak),
+            "per_frequency_max": float(np.max(np.max(diff, axis=0) / col)),
+            "per_frequency_max_top_quarter": float(np.max((np.max(diff, axis=0) / col)[-max(1, Iref.shape[1] // 4):])),
+            "l2_rel": float(np.linalg.norm(I - Iref) / np.linalg.norm(Iref)),
+            "per_direction_max": float(max(per_dir)),
+            "per_point_rel_max_bins_ge_1e-2_peak": float(np.max(diff[big] / Iref[big])) if big.any() else 0.0}
