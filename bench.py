@@ -64,9 +64,9 @@ def calibrate_copy(mib: int) -> int:
     return 0
 
 
-def profiled_traffic(profile: str):
+def profiled_traffic(profile: str, tile: dict):
     """HBM bytes per launch of the accumulate kernel from the committed rocprofv3 summary,
-    or None if the kernel source changed since those counters were taken."""
+    or None if the kernel source or the launch shape changed since those counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     src = os.path.join(ROOT, "paper_1802_03972_amd", "csrc", "rad_kernels.hip")
@@ -77,10 +77,11 @@ def profiled_traffic(profile: str):
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "tile"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    if vals.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+    tile_s = ",".join(str(tile[k]) for k in ("w_per_lane", "dir_per_wave", "waves", "wg_per_cu"))
+    if vals.get("kernel_source_sha256") != sha or vals.get("tile") != tile_s or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -175,7 +176,7 @@ def main() -> int:
     achieved = upd_per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md") if w is SINGLE else None,
+                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md", tile) if w is SINGLE else None,
                 "traffic_source": "profiles/k_accumulate_single_bunch_fp32.md (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, bytes per launch)",
                 "kernel": "k_accumulate", "avg_launch_ms": round(avg_ms, 4),
                 "updates_per_launch": int(upd_per_launch), "flops_per_update": FLOPS_PER_UPDATE,
@@ -270,6 +271,7 @@ def bench_batched(args) -> int:
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(0)
     batcher = rad.Batcher(max_items=len(ws))
+    gbatcher = rad.Batcher(max_items=len(ws), graph=True)
     slices = [[{k: v[j * w.n_particles:(j + 1) * w.n_particles] for k, v in d.items()} for j in range(kd)]
               for w, d in zip(ws, devs)]
     times = ws[0].times()
@@ -282,11 +284,14 @@ def bench_batched(args) -> int:
             for b, g in enumerate(grids):
                 g.push_step(float(times[j]), slices[b][j % kd], stream)
 
-    def batched():
+    def batched(bt=batcher):
         for g in grids:
             g.reset(stream)
         for j in range(n_steps):
-            batcher.push([(g, float(times[j]), 1, slices[b][j % kd]) for b, g in enumerate(grids)], stream)
+            bt.push([(g, float(times[j]), 1, slices[b][j % kd]) for b, g in enumerate(grids)], stream)
+
+    def batched_graph():
+        batched(gbatcher)
 
     def timed(fn, reps):
         fn()
@@ -310,6 +315,11 @@ def bench_batched(args) -> int:
     batcher.profile(False)
     log(f"[bench] batched persistent: {t_b * 1e3:.1f} ms per {n_steps} steps ({updates / t_b:.4e} updates/s)")
     I_b = [g.spectrum() for g in grids]
+    t_g = timed(batched_graph, reps)
+    I_g = [g.spectrum() for g in grids]
+    graph_equal = all(np.array_equal(a, b) for a, b in zip(I_b, I_g))
+    log(f"[bench] batched persistent, graph replays: {t_g * 1e3:.1f} ms per {n_steps} steps "
+        f"({updates / t_g:.4e} updates/s), bitwise equal to direct: {graph_equal}, {gbatcher.graph_stats()}")
     agree = None if I_pb is None else max(float(np.max(np.abs(a - b)) / np.max(a)) for a, b in zip(I_pb, I_b))
     avg_ms = prof["accumulate_ms"] / max(1, prof["launches"])
     achieved = prof["updates"] / max(1, prof["launches"]) * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
@@ -322,6 +332,7 @@ def bench_batched(args) -> int:
                    "time_steps": n_steps, "directions": ws[0].n_dir, "frequencies": ws[0].n_omega,
                    "distinct_generated_steps": kd, "updates_per_step": updates, "tile": grids[0].get_tile()},
         "per_bunch_launches": {"value": updates / t_pb, "ms_per_step": t_pb * 1e3},
+        "batched_graph": {"value": updates / t_g, "ms_per_step": t_g * 1e3, "bitwise_equal_to_direct": graph_equal},
         "speedup_vs_per_bunch": t_pb / t_b,
         "batched_vs_per_bunch_e_inf": agree,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -142,7 +142,9 @@ const char* rad_last_error(void);
  *   w_per_lane : frequencies held per lane (16 or 32)
  *   dir_per_wave: directions per wavefront (16, 32 or 64)
  *   waves      : wavefronts per workgroup (1..8)
- *   wg_per_cu  : workgroups per compute unit the split count aims at (>= 1)
+ *   wg_per_cu  : workgroups per compute unit in one launch (1..16): a push is cut into
+ *                CUs * wg_per_cu / tiles particle splits (the hardware runs as many of
+ *                them at once as registers and LDS allow)
  * rad_set_tile validates and applies it to later pushes. */
 typedef struct rad_tile {
     int32_t w_per_lane;
@@ -191,13 +193,31 @@ int rad_batcher_destroy(rad_batcher* b);
  * workgroup, so bunches of very different sizes share the device evenly; then one fold
  * launch adds the per-range partial tiles (fixed order, FP64) into each grid.  The result
  * equals that of pushing each item on its own, up to FP32 rounding of the partial sums.
- * Requirements: all grids on the batcher's device with the same precision mode and launch
- * tile (w_per_lane, dir_per_wave, waves), all items of one particle dtype.  Several items
- * may target the same grid.  Stream-ordered; the host blocks only to recycle a plan buffer
+ * Requirements: all grids on the batcher's device with the same precision mode, all items
+ * of one particle dtype; grid shapes may differ.  The launch shape is the batcher's own
+ * (rad_batcher_set_tile), independent of the grids' single-push tiles.  Several items may
+ * target the same grid.  Stream-ordered; the host blocks only to recycle a plan buffer
  * used two calls earlier.  Calls on one batcher must be ordered on one stream. */
 int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int32_t n_items, void* stream);
 
-/* Kernel timing of a batcher's launches (same semantics as rad_profile_*). */
+/* Launch shape of the batched kernel; NULL restores the default (the built-in heuristic
+ * for the first item's grid shape, chosen at each push).  wg_per_cu sets the number of
+ * workgroups (ranges) per compute unit of the persistent launch. */
+int rad_batcher_set_tile(rad_batcher* b, const rad_tile* t);
+int rad_batcher_get_tile(rad_batcher* b, rad_tile* t);
+
+/* Graph mode: the batcher lays every plan out with fixed capacities (max_items items,
+ * one range per workgroup of the whole device) and replays a hipGraph captured once per
+ * launch configuration -- upload of the plan from pinned host memory, the persistent
+ * accumulate launch and the fold -- instead of issuing the three operations each push.
+ * A plan that does not fit the capacities (more than 16 tiles per item on average) is
+ * launched directly.  If capture fails the batcher falls back to direct launches. */
+int rad_batcher_set_graph(rad_batcher* b, int enable);
+/* Captured graphs held, graph replays issued, capture failures. */
+int rad_batcher_graph_stats(rad_batcher* b, int64_t* graphs, int64_t* launches, int64_t* failures);
+
+/* Kernel timing of a batcher's launches (same semantics as rad_profile_*; in graph mode
+ * a replay is timed as a whole and reported as accumulate time). */
 int rad_batcher_profile_enable(rad_batcher* b, int enable);
 int rad_batcher_profile_read(rad_batcher* b, rad_profile_stats* out);
 
@@ -215,6 +235,7 @@ typedef struct rad_server_config {
     int64_t max_pending;    /* chunks submitted but not yet admitted; beyond it submit
                                returns RAD_ERR_QUEUE_FULL                                  */
     int32_t poll_us;        /* scheduler wake-up period when nothing moves [us] (>= 1)     */
+    int32_t use_graph;      /* 1: replay captured graphs for the batched launches          */
 } rad_server_config;
 
 /* Per-chunk timeline on the server clock [s since creation] and the launch it rode in. */

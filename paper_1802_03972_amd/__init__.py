@@ -63,13 +63,17 @@ class Grid:
 
     def __init__(self, dirs, omega0: float, domega: float, n_omega: int, shape="cic",
                  shape_len: float = 1e-7, dt: float = 5e-17, precision: int = PHASE_F64,
-                 device: int = 0):
+                 device: int = 0, tile="auto"):
+        """tile: "auto" applies the autotuner's table entry for this grid shape if present
+        (else the library's heuristic), None keeps the heuristic, or a dict of launch-shape
+        fields (w_per_lane, dir_per_wave, waves, wg_per_cu)."""
         L = _lib.lib()
         self._dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
         self.n_dir = int(self._dirs.shape[0])
         self.n_omega = int(n_omega)
         self.device = int(device)
         self.dt = float(dt)
+        self.precision = int(precision)
         self.omega0, self.domega = float(omega0), float(domega)
         sid = SHAPES[shape] if isinstance(shape, str) else int(shape)
         desc = _lib.GridDesc(self.n_dir, self._dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -78,6 +82,13 @@ class Grid:
         h = ctypes.c_void_p()
         _lib.check(L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc)))
         self._h = h
+        if tile == "auto":
+            from .autotune import lookup
+            t = lookup(self.n_dir, self.n_omega, int(precision))
+            if t is not None:
+                self.set_tile(**t)
+        elif tile is not None:
+            self.set_tile(**tile)
 
     # ------------------------------------------------------------------ lifetime
     def close(self) -> None:
@@ -182,12 +193,33 @@ class Grid:
 class Batcher:
     """Accumulates many (grid, steps, particles) items with one persistent launch."""
 
-    def __init__(self, device: int = 0, max_items: int = 256):
+    def __init__(self, device: int = 0, max_items: int = 256, graph: bool = False, tile="auto"):
+        """tile: "auto" applies the autotuner's batched-kernel entry for the first pushed
+        grid's shape (if any), None keeps the library default, or a dict of the four fields."""
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().rad_batcher_create(ctypes.byref(h), int(device), int(max_items)))
         self._h = h
         self.device = int(device)
         self.max_items = int(max_items)
+        self._auto = tile == "auto"
+        if isinstance(tile, dict):
+            self.set_tile(**tile)
+        if graph:
+            _lib.check(_lib.lib().rad_batcher_set_graph(h, 1))
+
+    def set_tile(self, **kw) -> None:
+        """Launch shape of the batched kernel (all four fields), or no arguments to restore
+        the default."""
+        if not kw:
+            _lib.check(_lib.lib().rad_batcher_set_tile(self._h, None))
+            return
+        t = _lib.Tile(*[int(kw[k]) for k, _ in _lib.Tile._fields_])
+        _lib.check(_lib.lib().rad_batcher_set_tile(self._h, ctypes.byref(t)))
+
+    def graph_stats(self) -> dict:
+        g, l, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.lib().rad_batcher_graph_stats(self._h, ctypes.byref(g), ctypes.byref(l), ctypes.byref(f)))
+        return {"graphs": g.value, "launches": l.value, "failures": f.value}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -204,6 +236,13 @@ class Batcher:
         """items: iterable of (grid, t0, n_steps, particles) with particles a dict of CUDA
         tensors holding n_steps * n_particles elements each (step-major)."""
         items = list(items)
+        if self._auto and items:
+            from .autotune import lookup_batch
+            g0 = items[0][0]
+            t = lookup_batch(g0.n_dir, g0.n_omega, g0.precision)
+            if t is not None:
+                self.set_tile(**t)
+            self._auto = False
         arr = (_lib.BatchItem * max(1, len(items)))()
         keep = []
         for k, (grid, t0, n_steps, parts) in enumerate(items):
@@ -232,9 +271,9 @@ class Server:
 
     def __init__(self, device: int = 0, hbm_budget: int = 1 << 30, max_batch: int = 64,
                  max_inflight: int = 2, max_admitted: int = 256, max_pending: int = 1 << 20,
-                 poll_us: int = 20):
+                 poll_us: int = 20, use_graph: bool = True):
         cfg = _lib.ServerConfig(int(device), int(hbm_budget), int(max_batch), int(max_inflight),
-                                int(max_admitted), int(max_pending), int(poll_us))
+                                int(max_admitted), int(max_pending), int(poll_us), 1 if use_graph else 0)
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().rad_server_create(ctypes.byref(h), ctypes.byref(cfg)))
         self._h = h

@@ -58,7 +58,7 @@ class BatchItem(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("max_admitted", ctypes.c_int32),
-                ("max_pending", ctypes.c_int64), ("poll_us", ctypes.c_int32)]
+                ("max_pending", ctypes.c_int64), ("poll_us", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class ChunkStats(ctypes.Structure):
@@ -98,6 +98,11 @@ SIGNATURES = {
     "rad_batcher_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.c_int32]),
     "rad_batcher_destroy": (ctypes.c_int, [_vp]),
     "rad_batcher_push": (ctypes.c_int, [_vp, ctypes.POINTER(BatchItem), ctypes.c_int32, _vp]),
+    "rad_batcher_set_graph": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rad_batcher_set_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
+    "rad_batcher_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
+    "rad_batcher_graph_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64)]),
     "rad_batcher_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "rad_batcher_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ProfileStats)]),
     "rad_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(ServerConfig)]),

@@ -1,0 +1,215 @@
+"""Launch-shape autotuner for the accumulate kernels.
+
+For a grid shape (directions x frequencies, particle dtype, arithmetic mode) it times every
+valid launch shape -- frequencies per lane (16, 32), directions per wave (16, 32, 64), waves
+per workgroup (1..8) and workgroups per compute unit in a launch (1, 2, 4) -- on synthetic
+particles held
+on the device, measuring whole pushes (accumulate + fold) with device events, and records
+the fastest in a JSON table next to this file.  `Grid(..., tile="auto")` applies the table
+entry for its shape when there is one (the library's built-in heuristic otherwise).
+
+    python -m paper_1802_03972_amd.autotune --dirs 128 --omegas 256 --dtype f32
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
+LDS_LIMIT = 160 * 1024
+CHUNK = 32
+
+
+def key(n_dir: int, n_omega: int, precision: int) -> str:
+    return f"{int(n_dir)}x{int(n_omega)}:p{int(precision)}"
+
+
+def load_table(path: str = TABLE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(n_dir: int, n_omega: int, precision: int, path: str = TABLE):
+    e = load_table(path).get(key(n_dir, n_omega, precision))
+    return None if e is None else e["tile"]
+
+
+def lds_bytes(w: int, dpw: int, waves: int) -> int:
+    td, to = dpw, waves * (64 // dpw) * w
+    return CHUNK * td * 16 + CHUNK * td * 8 + 11 * CHUNK * 8 + CHUNK * 8 + CHUNK * to * 4
+
+
+def candidates(n_dir: int, n_omega: int):
+    out = []
+    for w in (16, 32):
+        for dpw in (16, 32, 64):
+            for waves in (1, 2, 4, 8):
+                to = waves * (64 // dpw) * w
+                if to > 2 * n_omega and waves > 1:      # half the lanes or more would idle
+                    continue
+                if dpw > 2 * n_dir and dpw > 16:
+                    continue
+                lds = lds_bytes(w, dpw, waves)
+                if lds > LDS_LIMIT:
+                    continue
+                for wg in (1, 2, 4):                    # workgroups per CU in one launch
+                    out.append({"w_per_lane": w, "dir_per_wave": dpw, "waves": waves, "wg_per_cu": wg})
+    return out
+
+
+def synthetic_particles(n: int, dtype: str, device: int = 0, seed: int = 0) -> dict:
+    """Relativistic particles near the z axis (gamma 200, small transverse velocity);
+    values only need to be valid, the timing does not depend on them."""
+    import torch
+    g = torch.Generator(device=f"cuda:{device}").manual_seed(seed)
+    td = torch.float32 if dtype == "f32" else torch.float64
+    dev = f"cuda:{device}"
+    beta = (1.0 - 1.0 / 200.0 ** 2) ** 0.5
+    bx = (torch.rand(n, generator=g, device=dev, dtype=torch.float64) - 0.5) * 0.1
+    bz = torch.sqrt(beta ** 2 - bx ** 2)
+    f = {
+        "x": (torch.rand(n, generator=g, device=dev, dtype=torch.float64) - 0.5) * 2e-6,
+        "y": (torch.rand(n, generator=g, device=dev, dtype=torch.float64) - 0.5) * 2e-6,
+        "z": (torch.rand(n, generator=g, device=dev, dtype=torch.float64) - 0.5) * 2e-6,
+        "bx": bx, "by": torch.zeros(n, device=dev, dtype=torch.float64), "bz": bz,
+        "dbx": (torch.rand(n, generator=g, device=dev, dtype=torch.float64) - 0.5) * 2e12,
+        "dby": torch.zeros(n, device=dev, dtype=torch.float64),
+        "dbz": -bx * 1e10,
+        "w": torch.full((n,), 1e4, device=dev, dtype=torch.float64),
+    }
+    return {k: v.to(td).contiguous() for k, v in f.items()}
+
+
+def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_particles: int = 65536,
+         reps: int = 5, device: int = 0, verbose: bool = True) -> dict:
+    import numpy as np
+    import torch
+
+    from . import Grid
+
+    th = np.linspace(-0.02, 0.02, max(1, int(round(n_dir ** 0.5))))
+    dirs = []
+    for i in range(n_dir):
+        tx, ty = th[i % len(th)], th[(i // len(th)) % len(th)] * 0.5
+        dirs.append([tx, ty, (1 - tx * tx - ty * ty) ** 0.5])
+    parts = synthetic_particles(n_particles, dtype, device)
+    g = Grid(np.array(dirs), 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic", shape_len=1e-7,
+             dt=5e-17, precision=precision, device=device)
+    stream = torch.cuda.current_stream(device)
+    results = []
+    for c in candidates(n_dir, n_omega):
+        g.set_tile(**c)
+        g.push_step(0.0, parts, stream)        # warm-up (also instantiates the kernel)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(reps):
+            g.push_step(r * 5e-17, parts, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ups = n_particles * n_dir * n_omega / (ms * 1e-3)
+        results.append((ms, c, ups))
+        if verbose:
+            print(f"  {c}: {ms:.4f} ms/push, {ups:.3e} updates/s", flush=True)
+    g.close()
+    results.sort(key=lambda r: r[0])
+    ms, best, ups = results[0]
+    return {"tile": best, "ms_per_push": ms, "updates_per_s": ups, "n_particles": n_particles,
+            "candidates": len(results), "measured_at": time.strftime("%Y-%m-%d")}
+
+
+def batch_key(n_dir: int, n_omega: int, precision: int) -> str:
+    return "batch:" + key(n_dir, n_omega, precision)
+
+
+def lookup_batch(n_dir: int, n_omega: int, precision: int, path: str = TABLE):
+    e = load_table(path).get(batch_key(n_dir, n_omega, precision))
+    return None if e is None else e["tile"]
+
+
+def tune_batch(n_dir: int, n_omega: int, counts, dtype: str = "f32", precision: int = 0, reps: int = 3,
+               device: int = 0, verbose: bool = True) -> dict:
+    """Launch shape of the batched kernel for bunches of the given particle counts, all on
+    grids of n_dir x n_omega (one step per bunch per push)."""
+    import numpy as np
+    import torch
+
+    from . import Batcher, Grid
+
+    th = np.linspace(-0.02, 0.02, max(1, int(round(n_dir ** 0.5))))
+    dirs = np.array([[th[i % len(th)], th[(i // len(th)) % len(th)] * 0.5, 0.0] for i in range(n_dir)])
+    dirs[:, 2] = np.sqrt(1 - dirs[:, 0] ** 2 - dirs[:, 1] ** 2)
+    parts = [synthetic_particles(int(n), dtype, device, seed=k) for k, n in enumerate(counts)]
+    grids = [Grid(dirs, 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic", shape_len=1e-7, dt=5e-17,
+                  precision=precision, device=device, tile=None) for _ in counts]
+    b = Batcher(device=device, max_items=len(counts))
+    stream = torch.cuda.current_stream(device)
+    total = float(sum(counts)) * n_dir * n_omega
+    results = []
+    for c in candidates(n_dir, n_omega):
+        b.set_tile(**c)
+        items = [(g, 0.0, 1, p) for g, p in zip(grids, parts)]
+        b.push(items, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.push(items, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        results.append((ms, c, total / (ms * 1e-3)))
+        if verbose:
+            print(f"  batch {c}: {ms:.4f} ms/push, {total / (ms * 1e-3):.3e} updates/s", flush=True)
+    b.close()
+    for g in grids:
+        g.close()
+    results.sort(key=lambda r: r[0])
+    ms, best, ups = results[0]
+    return {"tile": best, "ms_per_push": ms, "updates_per_s": ups, "counts": [int(n) for n in counts],
+            "candidates": len(results), "measured_at": time.strftime("%Y-%m-%d")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description="tune the accumulate launch shape for grid shapes")
+    ap.add_argument("--dirs", type=int, nargs="+", required=True)
+    ap.add_argument("--omegas", type=int, nargs="+", required=True)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--particles", type=int, default=65536)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--out", default=TABLE, help="table to update (default: the package's table)")
+    ap.add_argument("--batch-counts", type=int, nargs="*", default=None,
+                    help="tune the batched kernel instead, for bunches of these particle counts")
+    a = ap.parse_args()
+    table = load_table(a.out)
+    if a.batch_counts:
+        for nd, no in zip(a.dirs, a.omegas):
+            print(f"tuning batched {nd} x {no}, counts {a.batch_counts}", flush=True)
+            r = tune_batch(nd, no, a.batch_counts, a.dtype, a.precision, max(1, a.reps // 2))
+            r["dtype"] = a.dtype
+            table[batch_key(nd, no, a.precision)] = r
+            print(f"best {r['tile']} at {r['updates_per_s']:.3e} updates/s", flush=True)
+        with open(a.out, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        print(f"wrote {a.out}")
+        return
+    for nd, no in zip(a.dirs, a.omegas):
+        print(f"tuning {nd} directions x {no} frequencies ({a.dtype}, precision {a.precision})", flush=True)
+        r = tune(nd, no, a.dtype, a.precision, a.particles, a.reps)
+        r["dtype"] = a.dtype
+        table[key(nd, no, a.precision)] = r
+        print(f"best {r['tile']} at {r['updates_per_s']:.3e} updates/s", flush=True)
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    print(f"wrote {a.out}")
+
+
+if __name__ == "__main__":
+    main()

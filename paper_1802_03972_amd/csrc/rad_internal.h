@@ -74,8 +74,12 @@ hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, 
 hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,
                                    float* seg_part, int dtype, int precision,
                                    const LaunchShape& s, int n_blocks, hipStream_t st);
-hipError_t launch_fold_batch(const FoldJob* jobs, int n_jobs, const int32_t* seg_list,
-                             const float* seg_part, int td, int to, hipStream_t st);
+// Kernel attributes only (no launch), so that a later stream capture records launches only.
+hipError_t prepare_accumulate_batch(int dtype, int precision, const LaunchShape& s);
+// n_jobs is read on the device (from n_jobs_dev) so that a captured graph can be replayed
+// with different plans; the grid is sized for max_jobs.
+hipError_t launch_fold_batch(const int32_t* n_jobs_dev, const FoldJob* jobs, int max_jobs,
+                             const int32_t* seg_list, const float* seg_part, int td, int to, hipStream_t st);
 hipError_t launch_finalize(const double* S, double* I, int n_dir, int n_omega, double C,
                            hipStream_t st);
 hipError_t launch_cartesian(const double* S, const double* dirs9, double* out, int n_dir,

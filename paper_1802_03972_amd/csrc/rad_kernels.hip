@@ -329,10 +329,11 @@ __global__ void k_fold(const float* __restrict__ part, double* __restrict__ S, i
 
 // Batched fold: for every (grid, tile) job and every in-grid point of the tile, add the
 // listed segments' partial values (in list order, FP64) into the grid's S.
-__global__ void k_fold_batch(const FoldJob* __restrict__ jobs, int n_jobs,
+__global__ void k_fold_batch(const int32_t* __restrict__ n_jobs_dev, const FoldJob* __restrict__ jobs,
                              const int32_t* __restrict__ seg_list, const float4* __restrict__ seg_part,
                              int TD, int TO)
 {
+    const int n_jobs = *n_jobs_dev;
     const int64_t per_job = (int64_t)TD * TO;
     const int64_t total = per_job * n_jobs;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -428,6 +429,7 @@ struct BatchArgs {
     const int32_t* wg_seg_begin;
     const BatchSeg* segs;
     float* seg_part;
+    bool prepare_only;   // only set the kernel's LDS attribute (done before a graph capture)
 };
 
 template <typename InT, int PREC, int W, int DPW>
@@ -442,6 +444,7 @@ hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks
         if (e != hipSuccess) return e;
         lds_allowed = lds;
     }
+    if (b.prepare_only) return hipSuccess;
     hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, b.items, b.wg_seg_begin,
                        b.segs, b.seg_part);
     return hipGetLastError();
@@ -492,17 +495,23 @@ hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin
                                    float* seg_part, int dtype, int precision,
                                    const LaunchShape& s, int n_blocks, hipStream_t st)
 {
-    const BatchArgs b{items, wg_seg_begin, segs, seg_part};
+    const BatchArgs b{items, wg_seg_begin, segs, seg_part, false};
     return dispatch_all(b, dtype, precision, s, n_blocks, st);
 }
 
-hipError_t launch_fold_batch(const FoldJob* jobs, int n_jobs, const int32_t* seg_list,
-                             const float* seg_part, int td, int to, hipStream_t st)
+hipError_t prepare_accumulate_batch(int dtype, int precision, const LaunchShape& s)
 {
-    if (n_jobs <= 0) return hipSuccess;
-    const int64_t total = (int64_t)n_jobs * td * to;
+    const BatchArgs b{nullptr, nullptr, nullptr, nullptr, true};
+    return dispatch_all(b, dtype, precision, s, 0, nullptr);
+}
+
+hipError_t launch_fold_batch(const int32_t* n_jobs_dev, const FoldJob* jobs, int max_jobs,
+                             const int32_t* seg_list, const float* seg_part, int td, int to, hipStream_t st)
+{
+    if (max_jobs <= 0) return hipSuccess;
+    const int64_t total = (int64_t)max_jobs * td * to;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fold_batch, dim3(blocks), dim3(256), 0, st, jobs, n_jobs, seg_list,
+    hipLaunchKernelGGL(k_fold_batch, dim3(blocks), dim3(256), 0, st, n_jobs_dev, jobs, seg_list,
                        reinterpret_cast<const float4*>(seg_part), td, to);
     return hipGetLastError();
 }

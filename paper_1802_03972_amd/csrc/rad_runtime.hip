@@ -264,7 +264,8 @@ int check_particles(const rad_particles* p)
     return RAD_OK;
 }
 
-void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0, int64_t n_per_step)
+void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0, int64_t n_per_step,
+              const rad_tile& t)
 {
     j.f[0] = p->x; j.f[1] = p->y; j.f[2] = p->z;
     j.f[3] = p->bx; j.f[4] = p->by; j.f[5] = p->bz;
@@ -278,8 +279,9 @@ void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0,
     j.domega = g->domega;
     j.n_dir = g->n_dir;
     j.n_omega = g->n_omega;
-    j.tiles_d = tiles_d(g);
-    j.tiles_w = tiles_w(g);
+    const int to = rad::tile_omegas(shape_of(t));
+    j.tiles_d = (g->n_dir + t.dir_per_wave - 1) / t.dir_per_wave;
+    j.tiles_w = (g->n_omega + to - 1) / to;
     j.err = g->d_err;
 }
 
@@ -292,13 +294,14 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
     const LaunchShape ls = shape_of(g->tile);
     const int td = tiles_d(g), tw = tiles_w(g), nt = td * tw;
     const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;
-    const int64_t per_launch_cap = (int64_t)g->part_splits * kMaxPerWorkgroup;
+    const int64_t target_splits = max_splits(g);   // <= part_splits (capacity may be larger)
+    const int64_t per_launch_cap = target_splits * kMaxPerWorkgroup;
     AccArgs a{};
-    fill_job(a.job, g, p, t0, n_per_step);
+    fill_job(a.job, g, p, t0, n_per_step, g->tile);
     for (int64_t i0 = 0; i0 < total; i0 += per_launch_cap) {
         const int64_t i1 = std::min(total, i0 + per_launch_cap);
         const int64_t nchunks = (i1 - i0 + rad::kChunk - 1) / rad::kChunk;
-        int64_t splits = std::min<int64_t>(g->part_splits, nchunks);
+        int64_t splits = std::min<int64_t>(target_splits, nchunks);
         const int64_t cps = (nchunks + splits - 1) / splits;
         splits = (nchunks + cps - 1) / cps;
         a.job.i_begin = i0;
@@ -660,6 +663,21 @@ extern "C" int rad_profile_read(rad_grid* g, rad_profile_stats* out)
 #include <map>
 #include <utility>
 
+struct BatchGraphKey {
+    int dtype, precision, w, dpw, waves, R, slot;
+    bool operator==(const BatchGraphKey& o) const
+    {
+        return dtype == o.dtype && precision == o.precision && w == o.w && dpw == o.dpw && waves == o.waves &&
+               R == o.R && slot == o.slot;
+    }
+};
+
+struct BatchGraph {
+    BatchGraphKey key;
+    int64_t gen;
+    hipGraphExec_t exec;
+};
+
 struct rad_batcher {
     int device = 0;
     int max_items = 0;
@@ -680,6 +698,15 @@ struct rad_batcher {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_acc, ev_fold;
     std::vector<hipEvent_t> ev_pool;
     int64_t prof_updates = 0;
+    // graph mode: captured [plan upload -> accumulate -> fold] per launch configuration
+    bool tile_set = false;       // launch shape of the batched kernel (else the built-in
+    rad_tile tile{};             // heuristic for the first item's grid shape)
+    bool graph_mode = false;
+    hipStream_t cap_stream = nullptr;
+    std::vector<BatchGraph> graphs;
+    int64_t graph_gen = 0;
+    int64_t graph_launches = 0;
+    int64_t graph_failures = 0;
 };
 
 namespace {
@@ -715,6 +742,9 @@ void free_batcher(rad_batcher* b)
         if (s.done) (void)hipEventDestroy(s.done);
     }
     if (b->seg_part) (void)hipFree(b->seg_part);
+    for (auto& ge : b->graphs) (void)hipGraphExecDestroy(ge.exec);
+    b->graphs.clear();
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     batch_release_events(b);
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
     delete b;
@@ -830,6 +860,7 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
     if (n_items > 0 && !items) return fail(RAD_ERR_INVALID_ARG, "items is NULL");
     // validation
     std::vector<ItemInfo> info;
+    std::vector<const rad_particles*> items_p;
     const rad_grid* g0 = nullptr;
     int dtype = -1;
     for (int32_t i = 0; i < n_items; ++i) {
@@ -848,19 +879,27 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         }
         if (itm.p.dtype != dtype) return fail(RAD_ERR_INVALID_ARG, "item %d: particle dtype differs within the batch", i);
         if (itm.grid->precision != g0->precision) return fail(RAD_ERR_INVALID_ARG, "item %d: precision mode differs", i);
-        const rad_tile& t = itm.grid->tile;
-        if (t.w_per_lane != g0->tile.w_per_lane || t.dir_per_wave != g0->tile.dir_per_wave || t.waves != g0->tile.waves)
-            return fail(RAD_ERR_INVALID_ARG, "item %d: launch tile differs from the first item's grid", i);
         ItemInfo in;
-        fill_job(in.job, itm.grid, &itm.p, itm.t0, itm.n_particles);
+        in.grid = itm.grid;
         in.job.i_begin = 0;
         in.job.i_end = (int64_t)itm.n_steps * itm.n_particles;
+        in.job.n_per_step = itm.n_particles;
+        in.job.t0 = itm.t0;
         in.chunks = (in.job.i_end + rad::kChunk - 1) / rad::kChunk;
-        in.iters = in.chunks * (int64_t)tiles_d(itm.grid) * tiles_w(itm.grid);
-        in.grid = itm.grid;
         info.push_back(in);
+        items_p.push_back(&itm.p);
     }
     if (info.empty()) return RAD_OK;
+    const rad_tile btile = b->tile_set ? b->tile : default_tile(g0->n_dir, g0->n_omega);
+    for (size_t i = 0; i < info.size(); ++i) {
+        ItemInfo& in = info[i];
+        const int64_t i_end = in.job.i_end, nps = in.job.n_per_step;
+        const double t0 = in.job.t0;
+        fill_job(in.job, in.grid, items_p[i], t0, nps, btile);
+        in.job.i_begin = 0;
+        in.job.i_end = i_end;
+        in.iters = in.chunks * (int64_t)in.job.tiles_d * in.job.tiles_w;
+    }
     DeviceGuard dg(b->device);
     hipStream_t st = (hipStream_t)stream;
     // earlier single-grid folds of these grids must land before the batch fold
@@ -877,23 +916,36 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         in.iter_begin = I;
         I += in.iters;
     }
-    const LaunchShape ls = shape_of(g0->tile);
+    const LaunchShape ls = shape_of(btile);
     const int TD = rad::tile_dirs(ls), TO = rad::tile_omegas(ls);
-    const int R_target = std::max(1, b->cus * g0->tile.wg_per_cu);
+    const int R_target = std::max(1, b->cus * btile.wg_per_cu);
     const int64_t per_launch = (int64_t)R_target * (kMaxPerWorkgroup / rad::kChunk);
     for (int64_t L0 = 0; L0 < I; L0 += per_launch) {
         const int64_t L1 = std::min(I, L0 + per_launch);
         const int R = (int)std::min<int64_t>(R_target, L1 - L0);
         LaunchPlan pl;
         build_plan(info, L0, L1, R, pl);
-        // plan bytes: items | wg_seg_begin | segs | jobs | seg_list
-        const size_t o_items = 0;
-        const size_t o_wsb = align_up(o_items + info.size() * sizeof(rad::Job), 16);
-        const size_t o_segs = align_up(o_wsb + pl.wg_seg_begin.size() * sizeof(int32_t), 16);
-        const size_t o_jobs = align_up(o_segs + pl.segs.size() * sizeof(rad::BatchSeg), 16);
-        const size_t o_list = align_up(o_jobs + pl.jobs.size() * sizeof(rad::FoldJob), 16);
-        const size_t bytes = align_up(o_list + pl.seg_list.size() * sizeof(int32_t), 16);
-        auto& sl = b->slot[b->next];
+        // Plan layout: header {n_items, n_segs, n_jobs, R} | items | wg_seg_begin | segs |
+        // jobs | seg_list.  In graph mode the capacities (and the launched grid) are fixed
+        // so one captured graph serves every plan that fits.
+        const int R_fixed = R_target;
+        const size_t segs_cap_g = (size_t)R_fixed + 16 * (size_t)b->max_items;
+        bool use_graph = b->graph_mode && pl.segs.size() <= segs_cap_g && pl.jobs.size() <= segs_cap_g &&
+                         pl.seg_list.size() <= segs_cap_g;
+        const int R_launch = use_graph ? R_fixed : R;
+        const size_t items_cap = use_graph ? (size_t)b->max_items : info.size();
+        const size_t segs_cap = use_graph ? segs_cap_g : pl.segs.size();
+        const size_t jobs_cap = use_graph ? segs_cap_g : pl.jobs.size();
+        const size_t list_cap = use_graph ? segs_cap_g : pl.seg_list.size();
+        const size_t o_hdr = 0;
+        const size_t o_items = 16;
+        const size_t o_wsb = align_up(o_items + items_cap * sizeof(rad::Job), 16);
+        const size_t o_segs = align_up(o_wsb + ((size_t)R_launch + 1) * sizeof(int32_t), 16);
+        const size_t o_jobs = align_up(o_segs + segs_cap * sizeof(rad::BatchSeg), 16);
+        const size_t o_list = align_up(o_jobs + jobs_cap * sizeof(rad::FoldJob), 16);
+        const size_t bytes = align_up(o_list + list_cap * sizeof(int32_t), 16);
+        const int slot_index = b->next;
+        auto& sl = b->slot[slot_index];
         b->next ^= 1;
         if (sl.used) RAD_HIP(hipEventSynchronize(sl.done));
         if (bytes > sl.cap) {
@@ -907,14 +959,21 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
                 hipMalloc((void**)&sl.dev, cap) != hipSuccess)
                 return fail(RAD_ERR_OOM, "cannot allocate a %zu B batch plan", cap);
             sl.cap = cap;
+            b->graph_gen += 1;   // captured graphs refer to the old buffers
         }
+        const int32_t hdr[4] = {(int32_t)info.size(), (int32_t)pl.segs.size(), (int32_t)pl.jobs.size(), (int32_t)R};
+        std::memcpy(sl.host + o_hdr, hdr, sizeof(hdr));
         for (size_t i = 0; i < info.size(); ++i) std::memcpy(sl.host + o_items + i * sizeof(rad::Job), &info[i].job, sizeof(rad::Job));
-        std::memcpy(sl.host + o_wsb, pl.wg_seg_begin.data(), pl.wg_seg_begin.size() * sizeof(int32_t));
+        {
+            int32_t* wsb = reinterpret_cast<int32_t*>(sl.host + o_wsb);
+            std::memcpy(wsb, pl.wg_seg_begin.data(), pl.wg_seg_begin.size() * sizeof(int32_t));
+            for (int r = R + 1; r <= R_launch; ++r) wsb[r] = (int32_t)pl.segs.size();   // idle workgroups
+        }
         std::memcpy(sl.host + o_segs, pl.segs.data(), pl.segs.size() * sizeof(rad::BatchSeg));
         std::memcpy(sl.host + o_jobs, pl.jobs.data(), pl.jobs.size() * sizeof(rad::FoldJob));
         std::memcpy(sl.host + o_list, pl.seg_list.data(), pl.seg_list.size() * sizeof(int32_t));
         // segment scratch
-        const size_t need = pl.segs.size() * (size_t)TD * TO * 4;
+        const size_t need = segs_cap * (size_t)TD * TO * 4;
         if (need > b->seg_part_floats) {
             if (b->seg_part) {
                 RAD_HIP(hipDeviceSynchronize());
@@ -926,8 +985,48 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
             if (hipMalloc((void**)&b->seg_part, alloc * sizeof(float)) != hipSuccess)
                 return fail(RAD_ERR_OOM, "cannot allocate %zu B of batch partial sums", alloc * sizeof(float));
             b->seg_part_floats = alloc;
+            b->graph_gen += 1;
         }
-        RAD_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st));
+        const rad::Job* d_items = reinterpret_cast<const rad::Job*>(sl.dev + o_items);
+        const int32_t* d_wsb = reinterpret_cast<const int32_t*>(sl.dev + o_wsb);
+        const rad::BatchSeg* d_segs = reinterpret_cast<const rad::BatchSeg*>(sl.dev + o_segs);
+        const int32_t* d_njobs = reinterpret_cast<const int32_t*>(sl.dev + o_hdr) + 2;
+        const rad::FoldJob* d_jobs = reinterpret_cast<const rad::FoldJob*>(sl.dev + o_jobs);
+        const int32_t* d_list = reinterpret_cast<const int32_t*>(sl.dev + o_list);
+        hipGraphExec_t exec = nullptr;
+        if (use_graph) {
+            const BatchGraphKey key{dtype, g0->precision, ls.w_per_lane, ls.dir_per_wave, ls.waves, R_launch, slot_index};
+            for (auto& ge : b->graphs)
+                if (ge.key == key && ge.gen == b->graph_gen) exec = ge.exec;
+            if (!exec) {
+                // capture [plan upload -> persistent accumulate -> fold] on the batcher's own stream
+                hipGraph_t graph = nullptr;
+                hipError_t e = rad::prepare_accumulate_batch(dtype, g0->precision, ls);
+                if (e == hipSuccess) e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    hipError_t e1 = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, b->cap_stream);
+                    if (e1 == hipSuccess)
+                        e1 = rad::launch_accumulate_batch(d_items, d_wsb, d_segs, b->seg_part, dtype, g0->precision,
+                                                          ls, R_launch, b->cap_stream);
+                    if (e1 == hipSuccess)
+                        e1 = rad::launch_fold_batch(d_njobs, d_jobs, (int)jobs_cap, d_list, b->seg_part, TD, TO,
+                                                    b->cap_stream);
+                    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+                    e = e1 != hipSuccess ? e1 : e2;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    exec = nullptr;
+                    b->graph_mode = false;   // fall back to direct launches from now on
+                    b->graph_failures += 1;
+                } else {
+                    b->graphs.push_back(BatchGraph{key, b->graph_gen, exec});
+                }
+            }
+            use_graph = exec != nullptr;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
         if (b->profiling) {
             RAD_HIP(batch_event(b, &e0));
@@ -945,20 +1044,31 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
                 const int64_t no = std::min(TO, in.job.n_omega - tw * TO);
                 b->prof_updates += (hi - lo) * nd * no;   // in-grid terms only
             }
-            RAD_HIP(hipEventRecord(e0, st));
         }
-        hipError_t e = rad::launch_accumulate_batch(
-            reinterpret_cast<const rad::Job*>(sl.dev + o_items), reinterpret_cast<const int32_t*>(sl.dev + o_wsb),
-            reinterpret_cast<const rad::BatchSeg*>(sl.dev + o_segs), b->seg_part, dtype, g0->precision, ls, R, st);
-        if (e != hipSuccess) return hip_fail(e, "batch accumulate launch");
-        if (b->profiling) {
-            RAD_HIP(hipEventRecord(e1, st));
-            RAD_HIP(hipEventRecord(e2, st));
+        if (use_graph) {
+            // timing of a replay covers the whole graph (upload, accumulate and fold)
+            if (b->profiling) RAD_HIP(hipEventRecord(e0, st));
+            RAD_HIP(hipGraphLaunch(exec, st));
+            b->graph_launches += 1;
+            if (b->profiling) {
+                RAD_HIP(hipEventRecord(e1, st));
+                RAD_HIP(hipEventRecord(e2, st));
+                RAD_HIP(hipEventRecord(e3, st));
+            }
+        } else {
+            RAD_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st));
+            if (b->profiling) RAD_HIP(hipEventRecord(e0, st));
+            hipError_t e = rad::launch_accumulate_batch(d_items, d_wsb, d_segs, b->seg_part, dtype, g0->precision,
+                                                        ls, R_launch, st);
+            if (e != hipSuccess) return hip_fail(e, "batch accumulate launch");
+            if (b->profiling) {
+                RAD_HIP(hipEventRecord(e1, st));
+                RAD_HIP(hipEventRecord(e2, st));
+            }
+            e = rad::launch_fold_batch(d_njobs, d_jobs, (int)jobs_cap, d_list, b->seg_part, TD, TO, st);
+            if (e != hipSuccess) return hip_fail(e, "batch fold launch");
+            if (b->profiling) RAD_HIP(hipEventRecord(e3, st));
         }
-        e = rad::launch_fold_batch(reinterpret_cast<const rad::FoldJob*>(sl.dev + o_jobs), (int)pl.jobs.size(),
-                                   reinterpret_cast<const int32_t*>(sl.dev + o_list), b->seg_part, TD, TO, st);
-        if (e != hipSuccess) return hip_fail(e, "batch fold launch");
-        if (b->profiling) RAD_HIP(hipEventRecord(e3, st));
         RAD_HIP(hipEventRecord(sl.done, st));
         sl.used = true;
     }
@@ -996,5 +1106,48 @@ extern "C" int rad_batcher_profile_read(rad_batcher* b, rad_profile_stats* out)
     b->prof_updates = 0;
     batch_release_events(b);
     *out = s;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_set_graph(rad_batcher* b, int enable)
+{
+    if (!b) return fail(RAD_ERR_INVALID_ARG, "batcher is NULL");
+    DeviceGuard dg(b->device);
+    if (enable && !b->cap_stream) {
+        if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(RAD_ERR_DEVICE, "cannot create the capture stream");
+    }
+    b->graph_mode = enable != 0;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_graph_stats(rad_batcher* b, int64_t* graphs, int64_t* launches, int64_t* failures)
+{
+    if (!b) return fail(RAD_ERR_INVALID_ARG, "batcher is NULL");
+    if (graphs) *graphs = (int64_t)b->graphs.size();
+    if (launches) *launches = b->graph_launches;
+    if (failures) *failures = b->graph_failures;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_set_tile(rad_batcher* b, const rad_tile* t)
+{
+    if (!b) return fail(RAD_ERR_INVALID_ARG, "batcher is NULL");
+    if (!t) {
+        b->tile_set = false;
+        return RAD_OK;
+    }
+    int rc = validate_tile(*t);
+    if (rc) return rc;
+    b->tile = *t;
+    b->tile_set = true;
+    return RAD_OK;
+}
+
+extern "C" int rad_batcher_get_tile(rad_batcher* b, rad_tile* t)
+{
+    if (!b || !t) return fail(RAD_ERR_INVALID_ARG, "batcher and tile must be non-NULL");
+    if (!b->tile_set) return fail(RAD_ERR_INVALID_ARG, "no launch shape set (the heuristic for the first item's grid is used)");
+    *t = b->tile;
     return RAD_OK;
 }

@@ -292,7 +292,9 @@ int rad_server_create(rad_server** out, const rad_server_config* cfg)
         return srv_fail(RAD_ERR_INVALID_ARG, "bad device");
     }
     int rc = rad_batcher_create(&s->batcher, cfg->device, cfg->max_batch);
+    if (rc == RAD_OK && cfg->use_graph) rc = rad_batcher_set_graph(s->batcher, 1);
     if (rc != RAD_OK) {
+        if (s->batcher) rad_batcher_destroy(s->batcher);
         delete s;
         return srv_fail(rc, std::string("batcher: ") + rad_last_error());
     }

@@ -1,0 +1,30 @@
+"""Autotuner host logic (no GPU): candidate launch shapes respect LDS and occupancy limits,
+and the table lookup keys on the grid shape and arithmetic mode."""
+import json
+
+from paper_1802_03972_amd import autotune
+
+
+def test_candidates_are_valid():
+    for nd, no in ((16, 64), (64, 256), (128, 256), (64, 1024), (128, 512)):
+        cs = autotune.candidates(nd, no)
+        assert cs
+        for c in cs:
+            assert c["w_per_lane"] in (16, 32) and c["dir_per_wave"] in (16, 32, 64)
+            assert 1 <= c["waves"] <= 8 and c["wg_per_cu"] in (1, 2, 4)
+            assert autotune.lds_bytes(c["w_per_lane"], c["dir_per_wave"], c["waves"]) <= autotune.LDS_LIMIT
+
+
+def test_lds_formula_matches_the_kernel_layout():
+    # geo float4 + tau double per (particle, direction), 11 staged doubles and (N, N^2) per
+    # particle, one float per (particle, frequency); 32-particle chunks
+    assert autotune.lds_bytes(32, 64, 8) == 32 * 64 * 24 + 32 * 88 + 32 * 8 + 32 * 256 * 4
+
+
+def test_table_lookup(tmp_path):
+    p = tmp_path / "t.json"
+    tile = {"w_per_lane": 32, "dir_per_wave": 64, "waves": 8, "wg_per_cu": 1}
+    p.write_text(json.dumps({autotune.key(128, 256, 0): {"tile": tile}}))
+    assert autotune.lookup(128, 256, 0, str(p)) == tile
+    assert autotune.lookup(128, 256, 1, str(p)) is None
+    assert autotune.lookup(64, 256, 0, str(tmp_path / "missing.json")) is None

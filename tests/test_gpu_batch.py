@@ -87,13 +87,35 @@ def test_several_items_on_one_grid(rad):
     assert e_inf(g_split.spectrum(), g_all.spectrum()) <= 1e-6
 
 
-def test_batch_rejects_mismatched_tiles(rad):
+def test_batch_mixes_grid_shapes_and_tiles(rad):
+    """Grids of different shapes and single-push tiles share one batched launch."""
+    w1 = SINGLE.scaled(n_particles=900, n_steps=2, nx_dir=4, ny_dir=8, n_omega=100, seed=41)
+    w2 = SINGLE.scaled(n_particles=1500, n_steps=2, nx_dir=8, ny_dir=8, n_omega=256, seed=42)
+    ws = [w1, w2]
+    sts = [w.steps() for w in ws]
+    grids = [grid_for(rad, w) for w in ws]
+    grids[0].set_tile(w_per_lane=16, dir_per_wave=16, waves=2, wg_per_cu=1)
+    devs = [to_device(st, w.in_dtype) for w, st in zip(ws, sts)]
+    b = rad.Batcher()
+    b.set_tile(w_per_lane=32, dir_per_wave=32, waves=4, wg_per_cu=2)
+    b.push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
+    for g, w, st, d in zip(grids, ws, sts, devs):
+        Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
+        assert e_inf(g.spectrum(), Iref) <= TOL
+        single = grid_for(rad, w)
+        single.push_steps(w.t0, w.n_steps, d)
+        assert e_inf(g.spectrum(), single.spectrum()) <= 1e-6
+
+
+def test_batch_rejects_mixed_precision(rad):
     bs = bunches([100, 100], steps=1)
-    grids = [grid_for(rad, w) for w, _ in bs]
-    grids[1].set_tile(w_per_lane=16)
+    g0 = grid_for(rad, bs[0][0])
+    w1 = bs[1][0]
+    g1 = rad.Grid(w1.directions(), w1.omega0, w1.domega, w1.n_omega, shape=w1.shape, shape_len=w1.shape_len,
+                  dt=w1.dt, precision=rad.ALL_F32)
     devs = [to_device(st, w.in_dtype) for w, st in bs]
     with pytest.raises(rad.RadError) as ei:
-        rad.Batcher().push([(g, w.t0, 1, d) for g, (w, _), d in zip(grids, bs, devs)])
+        rad.Batcher().push([(g0, 0.0, 1, devs[0]), (g1, 0.0, 1, devs[1])])
     assert ei.value.code == rad.RAD_ERR_INVALID_ARG
 
 
@@ -116,3 +138,27 @@ def test_batched_uneven_full_counts_one_step(rad):
         err = e_inf(I, Iref)
         print(f"batched_uneven bunch {k} (n={w.n_particles}): e_inf {err:.3e}")
         assert err <= TOL
+
+
+def test_graph_replays_match_direct_launches(rad):
+    """Graph mode: several replays, with eager work and synchronisation between them, each
+    bitwise equal to the direct-launch result of the same batch."""
+    import torch
+    bs = bunches([700, 5000, 64, 2100], steps=2)
+    devs = [to_device(st, w.in_dtype) for w, st in bs]
+    direct = [grid_for(rad, w) for w, _ in bs]
+    rad.Batcher(max_items=8).push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(direct, bs, devs)])
+    ref = [g.spectrum() for g in direct]
+    gb = rad.Batcher(max_items=8, graph=True)
+    graphed = [grid_for(rad, w) for w, _ in bs]
+    for rep in range(4):
+        for g in graphed:
+            g.reset()
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        gb.push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(graphed, bs, devs)])
+        torch.cuda.synchronize()
+        for g, r in zip(graphed, ref):
+            assert np.array_equal(g.spectrum(), r), rep
+        del junk
+    st = gb.graph_stats()
+    assert st["failures"] == 0 and st["launches"] == 4 and st["graphs"] >= 1
