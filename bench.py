@@ -330,7 +330,8 @@ def bench_batched(args) -> int:
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_uneven", "bunches": len(ws), "counts": list(mb.counts),
                    "time_steps": n_steps, "directions": ws[0].n_dir, "frequencies": ws[0].n_omega,
-                   "distinct_generated_steps": kd, "updates_per_step": updates, "tile": grids[0].get_tile()},
+                   "distinct_generated_steps": kd, "updates_per_step": updates,
+                   "tile": batcher.get_tile(), "per_bunch_tile": grids[0].get_tile()},
         "per_bunch_launches": {"value": updates / t_pb, "ms_per_step": t_pb * 1e3},
         "batched_graph": {"value": updates / t_g, "ms_per_step": t_g * 1e3, "bitwise_equal_to_direct": graph_equal},
         "speedup_vs_per_bunch": t_pb / t_b,

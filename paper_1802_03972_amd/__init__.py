@@ -216,6 +216,13 @@ class Batcher:
         t = _lib.Tile(*[int(kw[k]) for k, _ in _lib.Tile._fields_])
         _lib.check(_lib.lib().rad_batcher_set_tile(self._h, ctypes.byref(t)))
 
+    def get_tile(self):
+        """The batcher's launch shape, or None while the library default applies."""
+        t = _lib.Tile()
+        if _lib.lib().rad_batcher_get_tile(self._h, ctypes.byref(t)) != 0:
+            return None
+        return {k: getattr(t, k) for k, _ in _lib.Tile._fields_}
+
     def graph_stats(self) -> dict:
         g, l, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.check(_lib.lib().rad_batcher_graph_stats(self._h, ctypes.byref(g), ctypes.byref(l), ctypes.byref(f)))
