@@ -51,6 +51,12 @@ extern "C" {
 #define RAD_SHAPE_TSC   2 /* g = sinc^4(omega L / 2c)                                */
 #define RAD_SHAPE_QSC   3 /* g = sinc^6(omega L / 2c)                                */
 #define RAD_SHAPE_GAUSS 4 /* g = exp(-omega^2 L^2 / c^2), rho ~ exp(-x^2 / 2 L^2)      */
+/* Direction-dependent shapes of a cubic cell of side L (separable in x, y, z):
+ * g(n, omega) = prod_c sinc^(2p)(omega n_c L / 2c), p = 1 (CIC), 2 (TSC), 3 (QSC).  For
+ * n along an axis they reduce to the 1-D shapes above. */
+#define RAD_SHAPE_CIC3D 5
+#define RAD_SHAPE_TSC3D 6
+#define RAD_SHAPE_QSC3D 7
 
 /* ---- arithmetic modes ---- */
 #define RAD_PHASE_F64 0 /* default: geometry and phase t - n.r/c in FP64, FP32 update */
@@ -67,7 +73,7 @@ typedef struct rad_grid_desc {
     int32_t n_dir;       /* number of directions, >= 1                                  */
     const double* dirs;  /* HOST pointer, n_dir x 3 unit vectors (|n| within 1e-6 of 1);
                             copied at creation                                          */
-    double omega0;       /* first frequency [rad/s], >= 0                               */
+    double omega0;       /* first frequency [rad/s], >= 0 (ignored with `omegas`)       */
     double domega;       /* uniform spacing [rad/s], >= 0; omega_k = omega0 + k*domega  */
     int32_t n_omega;     /* number of frequencies, >= 1                                 */
     int32_t shape;       /* RAD_SHAPE_*                                                  */
@@ -75,6 +81,11 @@ typedef struct rad_grid_desc {
     double dt;           /* time step of Eq. 13 [s], > 0 (enters the prefactor only)   */
     int32_t precision;   /* RAD_PHASE_F64 or RAD_ALL_F32                                 */
     int32_t device;      /* HIP device ordinal                                          */
+    const double* omegas;/* optional HOST list of n_omega frequencies [rad/s] (finite, >= 0,
+                            any spacing, e.g. logarithmic); NULL: the uniform grid above.
+                            With a list, each term's phase is evaluated from FP64 (no
+                            frequency recurrence) and launch shapes use 16 frequencies
+                            per lane                                                     */
 } rad_grid_desc;
 
 /* One batch of macro-particles, structure of arrays, all fields the same type. */

@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "rad_oracle.c")
 
-SHAPE_IDS = {"point": 0, "cic": 1, "tsc": 2, "qsc": 3, "gauss": 4}
+SHAPE_IDS = {"point": 0, "cic": 1, "tsc": 2, "qsc": 3, "gauss": 4, "cic3d": 5, "tsc3d": 6, "qsc3d": 7}
 
 _lib = None
 
@@ -48,6 +48,8 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         L.oracle_shape_g.restype = ctypes.c_double
         L.oracle_shape_g.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.oracle_shape_g3.restype = ctypes.c_double
+        L.oracle_shape_g3.argtypes = [ctypes.c_int, ctypes.c_double, dp, ctypes.c_double]
         L.oracle_form_factor_sq.restype = ctypes.c_double
         L.oracle_form_factor_sq.argtypes = [ctypes.c_double, ctypes.c_double]
         L.oracle_amplitude.restype = None
@@ -99,6 +101,12 @@ def max_threads() -> int:
 def shape_g(shape, length: float, omega: float) -> float:
     """Normalised Table 1 shape factor |F~(omega)|^2."""
     return float(lib().oracle_shape_g(shape_id(shape), float(length), float(omega)))
+
+
+def shape_g3(shape, length: float, n, omega: float) -> float:
+    """Cubic-cell (3-D) shape factor g(n, omega)."""
+    n = np.ascontiguousarray(n, np.float64)
+    return float(lib().oracle_shape_g3(shape_id(shape), float(length), _dp(n), float(omega)))
 
 
 def form_factor_sq(N: float, g: float) -> float:

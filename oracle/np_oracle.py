@@ -33,6 +33,14 @@ def shape_g(shape: str, length: float, omega):
     return s ** p
 
 
+def shape_g3(shape: str, length: float, n, omega):
+    """Cubic cell: product over x, y, z of the 1-D factor at omega * |n_c|."""
+    n = np.asarray(n, np.float64)
+    base = shape[:-2]
+    return (shape_g(base, length, np.asarray(omega) * abs(n[0])) * shape_g(base, length, np.asarray(omega) * abs(n[1]))
+            * shape_g(base, length, np.asarray(omega) * abs(n[2])))
+
+
 def form_factor_sq(N, g):
     N = np.asarray(N, np.float64)
     return N + (N * N - N) * g
@@ -61,9 +69,9 @@ def spectrum_complex(samples: dict, dirs, omegas, shape: str, shape_len: float,
     w = np.asarray(samples["w"], np.float64).reshape(-1)
     dirs = np.asarray(dirs, np.float64).reshape(-1, 3)
     omegas = np.asarray(omegas, np.float64).reshape(-1)
-    g = shape_g(shape, shape_len, omegas)                     # (K,)
     out = np.zeros((dirs.shape[0], omegas.shape[0], 3), np.complex128)
     for d, n in enumerate(dirs):
+        g = shape_g3(shape, shape_len, n, omegas) if shape.endswith("3d") else shape_g(shape, shape_len, omegas)
         for s0 in range(0, t.shape[0], chunk):
             sl = slice(s0, s0 + chunk)
             A = amplitude(n, b[sl], db[sl])                   # (P, 3)
@@ -94,6 +102,19 @@ def sample_offsets(rng: np.random.Generator, shape: str, length: float, size) ->
     for _ in range(k):
         out = out + rng.uniform(-0.5 * length, 0.5 * length, size)
     return out
+
+
+def sample_offsets3(rng: np.random.Generator, shape: str, length: float, size) -> np.ndarray:
+    """3-D electron offsets (..., 3) filling a cubic cell: each axis independently drawn from
+    the 1-D density of the base shape."""
+    base = shape[:-2]
+    return np.stack([sample_offsets(rng, base, length, size) for _ in range(3)], axis=-1)
+
+
+def electron_phase_sum3(offsets: np.ndarray, n, omega: float) -> np.ndarray:
+    """Eq. 8 with 3-D offsets (R, N, 3): |sum_k exp(-i omega n.r_k / c)|^2."""
+    z = np.exp(-1j * omega * (offsets @ np.asarray(n, np.float64)) / C).sum(axis=-1)
+    return np.abs(z) ** 2
 
 
 def electron_phase_sum(offsets: np.ndarray, omega: float) -> np.ndarray:

@@ -29,8 +29,12 @@
  *    g(omega) = |F~(omega)|^2 with F~(0) = 1:
  *      CIC sinc^2(omega D / 2c), TSC sinc^4, QSC sinc^6 (sinc(x) = sin(x)/x),
  *      Gauss exp(-omega^2 sigma^2 / c^2) for rho ~ exp(-x^2 / 2 sigma^2).
- *    The shape factor is applied along n independently of the direction (the paper
- *    takes n = e_x without loss of generality when deriving it).
+ *    For the 1-D shapes the factor is applied along n independently of the direction
+ *    (the paper takes n = e_x without loss of generality when deriving it).
+ *  - Shapes 5-7 are the cubic-cell versions (side D): the density is the product of the
+ *    1-D density along x, y and z, so its transform at wave vector omega n / c is the
+ *    product of the 1-D transforms at omega n_c / c:
+ *      g(n, omega) = prod_c sinc^(2p)(omega n_c D / 2c),  p = 1 (CIC), 2 (TSC), 3 (QSC).
  *  - c in Eq. 1 is the speed of light (the text calls it a mass).
  *  - Sums are accumulated with Neumaier compensation so that the reference value does
  *    not drift over ~1e8 terms; this does not change which terms are summed.
@@ -49,7 +53,7 @@ static const double ORC_EPS0 = 8.8541878128e-12;  /* vacuum permittivity [F/m]  
 static const double ORC_PI = 3.14159265358979323846;
 
 enum { ORC_SHAPE_POINT = 0, ORC_SHAPE_CIC = 1, ORC_SHAPE_TSC = 2, ORC_SHAPE_QSC = 3,
-       ORC_SHAPE_GAUSS = 4 };
+       ORC_SHAPE_GAUSS = 4, ORC_SHAPE_CIC3D = 5, ORC_SHAPE_TSC3D = 6, ORC_SHAPE_QSC3D = 7 };
 
 /* Table 1, normalised: squared Fourier transform of the unit-charge shape. */
 double oracle_shape_g(int shape, double len, double omega)
@@ -66,6 +70,15 @@ double oracle_shape_g(int shape, double len, double omega)
     if (shape == ORC_SHAPE_TSC) return s2 * s2;
     if (shape == ORC_SHAPE_QSC) return s2 * s2 * s2;
     return NAN;
+}
+
+/* Cubic-cell shapes: product of the 1-D factor over the three axes at omega * |n_c|. */
+double oracle_shape_g3(int shape, double len, const double n[3], double omega)
+{
+    int base = shape - ORC_SHAPE_CIC3D + ORC_SHAPE_CIC;
+    return oracle_shape_g(base, len, omega * fabs(n[0])) *
+           oracle_shape_g(base, len, omega * fabs(n[1])) *
+           oracle_shape_g(base, len, omega * fabs(n[2]));
 }
 
 /* Eq. 12: F^2 = N + (N^2 - N) g  (incoherent + coherent part). */
@@ -147,7 +160,7 @@ int oracle_spectrum_complex(int64_t n_samples, const double* t,
                             int shape, double shape_len, double* S_out)
 {
     if (n_samples < 0 || n_dir < 0 || n_omega < 0 || !S_out) return -1;
-    if (shape < ORC_SHAPE_POINT || shape > ORC_SHAPE_GAUSS) return -1;
+    if (shape < ORC_SHAPE_POINT || shape > ORC_SHAPE_QSC3D) return -1;
     int64_t n_points = (int64_t)n_dir * n_omega;
 
 #pragma omp parallel for schedule(dynamic, 1)
@@ -156,7 +169,8 @@ int oracle_spectrum_complex(int64_t n_samples, const double* t,
         int k = (int)(p % n_omega);
         const double* n = dirs + 3 * d;
         double omega = omegas[k];
-        double g = oracle_shape_g(shape, shape_len, omega);
+        double g = shape >= ORC_SHAPE_CIC3D ? oracle_shape_g3(shape, shape_len, n, omega)
+                                            : oracle_shape_g(shape, shape_len, omega);
         nsum acc[6] = { { 0, 0 }, { 0, 0 }, { 0, 0 }, { 0, 0 }, { 0, 0 }, { 0, 0 } };
         for (int64_t i = 0; i < n_samples; ++i) {
             double beta[3] = { bx[i], by[i], bz[i] };

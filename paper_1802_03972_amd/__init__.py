@@ -63,13 +63,18 @@ class Grid:
 
     def __init__(self, dirs, omega0: float, domega: float, n_omega: int, shape="cic",
                  shape_len: float = 1e-7, dt: float = 5e-17, precision: int = PHASE_F64,
-                 device: int = 0, tile="auto"):
-        """tile: "auto" applies the autotuner's table entry for this grid shape if present
+                 device: int = 0, tile="auto", omegas=None):
+        """omegas: optional explicit frequency list (any spacing); then omega0/domega are
+        ignored and n_omega is its length.
+        tile: "auto" applies the autotuner's table entry for this grid shape if present
         (else the library's heuristic), None keeps the heuristic, or a dict of launch-shape
         fields (w_per_lane, dir_per_wave, waves, wg_per_cu)."""
         L = _lib.lib()
         self._dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
         self.n_dir = int(self._dirs.shape[0])
+        self._omegas = None if omegas is None else np.ascontiguousarray(omegas, np.float64).reshape(-1)
+        if self._omegas is not None:
+            n_omega = self._omegas.size
         self.n_omega = int(n_omega)
         self.device = int(device)
         self.dt = float(dt)
@@ -78,16 +83,19 @@ class Grid:
         sid = SHAPES[shape] if isinstance(shape, str) else int(shape)
         desc = _lib.GridDesc(self.n_dir, self._dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                              self.omega0, self.domega, self.n_omega, sid, float(shape_len),
-                             self.dt, int(precision), self.device)
+                             self.dt, int(precision), self.device,
+                             None if self._omegas is None else
+                             self._omegas.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         h = ctypes.c_void_p()
         _lib.check(L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc)))
         self._h = h
-        if tile == "auto":
+        self.variant = (1 if self._omegas is not None else 0) | (2 if sid >= 5 else 0)
+        if tile == "auto" and self.variant == 0:
             from .autotune import lookup
             t = lookup(self.n_dir, self.n_omega, int(precision))
             if t is not None:
                 self.set_tile(**t)
-        elif tile is not None:
+        elif isinstance(tile, dict):
             self.set_tile(**tile)
 
     # ------------------------------------------------------------------ lifetime
@@ -246,7 +254,7 @@ class Batcher:
         if self._auto and items:
             from .autotune import lookup_batch
             g0 = items[0][0]
-            t = lookup_batch(g0.n_dir, g0.n_omega, g0.precision)
+            t = lookup_batch(g0.n_dir, g0.n_omega, g0.precision) if g0.variant == 0 else None
             if t is not None:
                 self.set_tile(**t)
             self._auto = False

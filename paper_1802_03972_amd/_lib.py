@@ -14,7 +14,7 @@ RAD_ERR_DEVICE = -3
 RAD_ERR_BAD_DATA = -4
 RAD_ERR_QUEUE_FULL = -5
 
-SHAPES = {"point": 0, "cic": 1, "tsc": 2, "qsc": 3, "gauss": 4}
+SHAPES = {"point": 0, "cic": 1, "tsc": 2, "qsc": 3, "gauss": 4, "cic3d": 5, "tsc3d": 6, "qsc3d": 7}
 PHASE_F64 = 0
 ALL_F32 = 1
 F32 = 0
@@ -32,7 +32,8 @@ class GridDesc(ctypes.Structure):
                 ("omega0", ctypes.c_double), ("domega", ctypes.c_double),
                 ("n_omega", ctypes.c_int32), ("shape", ctypes.c_int32),
                 ("shape_len", ctypes.c_double), ("dt", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("omegas", ctypes.POINTER(ctypes.c_double))]
 
 
 class Particles(ctypes.Structure):

@@ -18,12 +18,18 @@ struct Job {
     double t0, dt;          // t_j = t0 + j * dt
     const double* dirs9;    // [n_dir][9]: n, e1, e2 (e1, e2 span the plane normal to n)
     const double* omega;    // [n_omega]
-    const float2* gtab;     // [n_omega]: (g, 1 - g) of the shape
-    double domega;
+    const float2* gtab;     // [n_omega]: (g, 1 - g) of a 1-D shape
+    const float* g3;        // [n_dir][n_omega]: g of a 3-D (direction-dependent) shape, or null
+    double domega;          // uniform spacing (unused for explicit, non-uniform frequency lists)
     int32_t n_dir, n_omega;
     int32_t tiles_d, tiles_w;
     int* err;               // sticky data-error flag of the grid
 };
+
+// Kernel variant bits: how the phase is advanced along the lane's frequencies and where
+// the form factor comes from.
+constexpr int kVarDirect = 1;   // explicit frequency list: phase from FP64 per term (no recurrence)
+constexpr int kVarShape3 = 2;   // direction-dependent shape factor g(n, omega)
 
 // Arguments of the per-grid accumulate kernel: block b handles tile b % ntiles of split
 // b / ntiles, i.e. chunks [split * chunks_per_split, +chunks_per_split) of the job.
@@ -51,9 +57,10 @@ struct FoldJob {
 };
 
 struct LaunchShape {
-    int w_per_lane;    // 16 | 32
+    int w_per_lane;    // 16 | 32 (16 only for variant != 0)
     int dir_per_wave;  // 16 | 32 | 64
     int waves;         // 1..8
+    int variant = 0;   // kVarDirect | kVarShape3 bits
 };
 
 inline int tile_dirs(const LaunchShape& s) { return s.dir_per_wave; }

@@ -67,7 +67,7 @@ __device__ __forceinline__ double load_wide(const void* p, int64_t i)
 
 // Per (particle, direction) geometry.  Writes A1, A2 (FP32), w = exp(i domega tau) and
 // tau/(2 pi) (FP64).
-template <int PREC>
+template <int PREC, bool WANT_W>
 __device__ __forceinline__ void particle_direction_setup(const double* __restrict__ raw, int m,
                                                          const double* __restrict__ dv,
                                                          double domega, float4& geo,
@@ -100,9 +100,13 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         A2 = -static_cast<float>(b2 * nbd + q2 * D) * inv;
         const double tau = t - (nx * x + ny * y + nz * z) * kInvC;
         ph = tau * kInv2Pi;
-        double rw = domega * ph;
-        rw -= floor(rw);
-        sincos_rev_fast(static_cast<float>(rw), wi, wr);
+        wr = 1.f;
+        wi = 0.f;
+        if constexpr (WANT_W) {
+            double rw = domega * ph;
+            rw -= floor(rw);
+            sincos_rev_fast(static_cast<float>(rw), wi, wr);
+        }
         bad = !(D > 0.0) || !(N >= 0.0) || !isfinite(N) || !isfinite(ph) || !isfinite(A1) ||
               !isfinite(A2);
     } else {
@@ -124,9 +128,13 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         A2 = -(b2 * nbd + q2 * D) * inv;
         const float tau = (float)t - (fnx * fx + fny * fy + fnz * fz) * (float)kInvC;
         const float phf = tau * (float)kInv2Pi;
-        float rw = (float)domega * phf;
-        rw -= floorf(rw);
-        sincos_rev_fast(rw, wi, wr);
+        wr = 1.f;
+        wi = 0.f;
+        if constexpr (WANT_W) {
+            float rw = (float)domega * phf;
+            rw -= floorf(rw);
+            sincos_rev_fast(rw, wi, wr);
+        }
         ph = (double)phf;
         bad = !(D > 0.0f) || !(N >= 0.0) || !isfinite(N) || !isfinite(phf) || !isfinite(A1) ||
               !isfinite(A2);
@@ -140,7 +148,7 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
 // partial tile: element (omega o, direction d) of the tile goes to out[o * row + d] (as
 // (S1r, S1i, S2r, S2i)) when it lies inside the grid.  Every thread of the workgroup must
 // call this with the same arguments; LDS is reused chunk by chunk.
-template <typename InT, int PREC, int W, int DPW>
+template <typename InT, int PREC, int W, int DPW, int V>
 __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, int64_t c_begin,
                                                  int64_t c_end, float4* __restrict__ out, int row,
                                                  float4* smem4)
@@ -165,9 +173,23 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     float2* nw = reinterpret_cast<float2*>(raw + 11 * P);            // [P]: (N, N^2) in FP32
     float* ff = reinterpret_cast<float*>(nw + P);                    // [P][TO]
 
+    constexpr bool DIRECT = (V & kVarDirect) != 0;
+    constexpr bool SHAPE3 = (V & kVarShape3) != 0;
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
     const double om_first = j.omega[o_first < j.n_omega ? o_first : j.n_omega - 1];
+    // explicit frequencies (direct phase) and direction-dependent shape factors of this lane
+    double om[DIRECT ? W : 1];
+    float gl[SHAPE3 ? W : 1];
+    {
+        const int dc = d < j.n_dir ? d : j.n_dir - 1;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int oc = o_first + k < j.n_omega ? o_first + k : j.n_omega - 1;
+            if constexpr (DIRECT) om[k] = j.omega[oc];
+            if constexpr (SHAPE3) gl[k] = j.g3[(int64_t)dc * j.n_omega + oc];
+        }
+    }
 
     float s1r[W], s1i[W], s2r[W], s2i[W];
 #pragma unroll
@@ -203,13 +225,13 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             dg = dg < j.n_dir ? dg : j.n_dir - 1;
             float4 gv;
             double ph;
-            particle_direction_setup<PREC>(raw, m, j.dirs9 + 9 * dg, j.domega, gv, ph, j.err);
+            particle_direction_setup<PREC, !DIRECT>(raw, m, j.dirs9 + 9 * dg, j.domega, gv, ph, j.err);
             geo[i] = gv;
             taus[i] = ph;
         }
         // 3. per (particle, frequency) form-factor weight F = sqrt(N^2 g + N (1 - g)) (Eq. 12),
         //    FP32; frequencies outside the grid get F = 0 and contribute nothing.
-        for (int o = tid; o < TO; o += nt) {
+        for (int o = tid; o < (SHAPE3 ? 0 : TO); o += nt) {
             const int og = tw * TO + o;
             float2 g = make_float2(0.f, 0.f);
             if (og < j.n_omega) g = j.gtab[og];
@@ -225,35 +247,65 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
         for (int m = 0; m < P; ++m) {
             const float4 gm = geo[m * TD + dl];
             const double ph = taus[m * TD + dl];
-            float zr, zi;
-            if constexpr (PREC == 0) {
-                double rv = om_first * ph;
-                rv -= floor(rv);
-                sincos_rev_fast(static_cast<float>(rv), zi, zr);
-            } else {
-                float rv = (float)om_first * (float)ph;
-                rv -= floorf(rv);
-                sincos_rev_fast(rv, zi, zr);
+            float zr = 1.f, zi = 0.f;
+            if constexpr (!DIRECT) {
+                if constexpr (PREC == 0) {
+                    double rv = om_first * ph;
+                    rv -= floor(rv);
+                    sincos_rev_fast(static_cast<float>(rv), zi, zr);
+                } else {
+                    float rv = (float)om_first * (float)ph;
+                    rv -= floorf(rv);
+                    sincos_rev_fast(rv, zi, zr);
+                }
             }
             const float A1 = gm.x, A2 = gm.y, wr = gm.z, wi = gm.w;
             const float4* fq = reinterpret_cast<const float4*>(ff + m * TO + ob * W);
+            float Nm = 0.f, NN1 = 0.f;
+            if constexpr (SHAPE3) {
+                const float2 Nv = nw[m];
+                Nm = Nv.x;
+                NN1 = Nv.y - Nv.x;   // N^2 - N
+            }
 #pragma unroll
             for (int q = 0; q < W / 4; ++q) {
-                const float4 F4 = fq[q];
-                const float Fv[4] = {F4.x, F4.y, F4.z, F4.w};
+                float Fv[4];
+                if constexpr (SHAPE3) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)   // F^2 = N + (N^2 - N) g(n, omega) (Eq. 12)
+                        Fv[u] = __builtin_amdgcn_sqrtf(fmaxf(fmaf(NN1, gl[4 * q + u], Nm), 0.f));
+                } else {
+                    const float4 F4 = fq[q];
+                    Fv[0] = F4.x; Fv[1] = F4.y; Fv[2] = F4.z; Fv[3] = F4.w;
+                }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int k = 4 * q + u;
+                    if constexpr (DIRECT) {
+                        // explicit frequency list: each term's phase from the FP64 product,
+                        // reduced to [0, 1) revolutions before leaving FP64
+                        if constexpr (PREC == 0) {
+                            double rv = om[k] * ph;
+                            rv -= floor(rv);
+                            sincos_rev_fast(static_cast<float>(rv), zi, zr);
+                        } else {
+                            float rv = (float)om[k] * (float)ph;
+                            rv -= floorf(rv);
+                            sincos_rev_fast(rv, zi, zr);
+                        }
+                    }
                     const float ur = Fv[u] * zr;
                     const float ui = Fv[u] * zi;
                     s1r[k] = fmaf(A1, ur, s1r[k]);
                     s1i[k] = fmaf(A1, ui, s1i[k]);
                     s2r[k] = fmaf(A2, ur, s2r[k]);
                     s2i[k] = fmaf(A2, ui, s2i[k]);
-                    const float nr = fmaf(zr, wr, -(zi * wi));
-                    const float ni = fmaf(zr, wi, zi * wr);
-                    zr = nr;
-                    zi = ni;
+                    if constexpr (!DIRECT) {
+                        const float nr = fmaf(zr, wr, -(zi * wi));
+                        const float ni = fmaf(zr, wi, zi * wr);
+                        zr = nr;
+                        zi = ni;
+                    }
                 }
             }
         }
@@ -271,7 +323,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     }
 }
 
-template <typename InT, int PREC, int W, int DPW>
+template <typename InT, int PREC, int W, int DPW, int V>
 __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
 {
     extern __shared__ float4 smem4[];
@@ -290,13 +342,13 @@ __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
     // partial layout [split][omega][dir]
     float4* out = reinterpret_cast<float4*>(a.part) +
                   ((int64_t)split * a.job.n_omega + (int64_t)tw * TO) * a.job.n_dir + td * TD;
-    accumulate_range<InT, PREC, W, DPW>(a.job, td, tw, c_begin, c_end, out, a.job.n_dir, smem4);
+    accumulate_range<InT, PREC, W, DPW, V>(a.job, td, tw, c_begin, c_end, out, a.job.n_dir, smem4);
 }
 
 // Persistent batched accumulate: block r processes segments [wg_seg_begin[r], wg_seg_begin[r+1]),
 // each a chunk range of one (item, tile); segment s writes its partial tile [TO][TD] at
 // seg_part + s * TO * TD (float4 units).
-template <typename InT, int PREC, int W, int DPW>
+template <typename InT, int PREC, int W, int DPW, int V>
 __global__ void __launch_bounds__(512) k_accumulate_batch(const Job* __restrict__ items,
                                                           const int32_t* __restrict__ wg_seg_begin,
                                                           const BatchSeg* __restrict__ segs,
@@ -312,7 +364,7 @@ __global__ void __launch_bounds__(512) k_accumulate_batch(const Job* __restrict_
         const int td = sg.tile % j.tiles_d;
         const int tw = sg.tile / j.tiles_d;
         float4* out = reinterpret_cast<float4*>(seg_part) + (int64_t)s * TO * TD;
-        accumulate_range<InT, PREC, W, DPW>(j, td, tw, sg.c_begin, sg.c_end, out, TD, smem4);
+        accumulate_range<InT, PREC, W, DPW, V>(j, td, tw, sg.c_begin, sg.c_end, out, TD, smem4);
     }
 }
 
@@ -408,10 +460,10 @@ __global__ void k_trig_probe(const float* in, float* out, int n)
 
 inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename InT, int PREC, int W, int DPW>
+template <typename InT, int PREC, int W, int DPW, int V>
 hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
 {
-    auto kern = k_accumulate<InT, PREC, W, DPW>;
+    auto kern = k_accumulate<InT, PREC, W, DPW, V>;
     const size_t lds = acc_lds_bytes(s);
     static size_t lds_allowed = 64 * 1024;  // per instantiation; the attribute is process-wide
     if (lds > lds_allowed) {
@@ -432,10 +484,10 @@ struct BatchArgs {
     bool prepare_only;   // only set the kernel's LDS attribute (done before a graph capture)
 };
 
-template <typename InT, int PREC, int W, int DPW>
+template <typename InT, int PREC, int W, int DPW, int V>
 hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks, hipStream_t st)
 {
-    auto kern = k_accumulate_batch<InT, PREC, W, DPW>;
+    auto kern = k_accumulate_batch<InT, PREC, W, DPW, V>;
     const size_t lds = acc_lds_bytes(s);
     static size_t lds_allowed = 64 * 1024;
     if (lds > lds_allowed) {
@@ -454,19 +506,29 @@ hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks
 template <typename InT, int PREC, typename A>
 hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStream_t st)
 {
-#define RAD_SHAPE_CASE(WW, DD)                                                        \
-    if (s.w_per_lane == WW && s.dir_per_wave == DD) {                                 \
+#define RAD_SHAPE_CASE(WW, DD, VV)                                                    \
+    if (s.w_per_lane == WW && s.dir_per_wave == DD && s.variant == VV) {              \
         if constexpr (std::is_same<A, AccArgs>::value)                                \
-            return launch_acc_t<InT, PREC, WW, DD>(a, s, n_blocks, st);               \
+            return launch_acc_t<InT, PREC, WW, DD, VV>(a, s, n_blocks, st);           \
         else                                                                          \
-            return launch_batch_t<InT, PREC, WW, DD>(a, s, n_blocks, st);             \
+            return launch_batch_t<InT, PREC, WW, DD, VV>(a, s, n_blocks, st);         \
     }
-    RAD_SHAPE_CASE(32, 64)
-    RAD_SHAPE_CASE(32, 32)
-    RAD_SHAPE_CASE(32, 16)
-    RAD_SHAPE_CASE(16, 64)
-    RAD_SHAPE_CASE(16, 32)
-    RAD_SHAPE_CASE(16, 16)
+    RAD_SHAPE_CASE(32, 64, 0)
+    RAD_SHAPE_CASE(32, 32, 0)
+    RAD_SHAPE_CASE(32, 16, 0)
+    RAD_SHAPE_CASE(16, 64, 0)
+    RAD_SHAPE_CASE(16, 32, 0)
+    RAD_SHAPE_CASE(16, 16, 0)
+    // explicit frequency lists and 3-D shapes: 16 frequencies per lane (register budget)
+    RAD_SHAPE_CASE(16, 64, 1)
+    RAD_SHAPE_CASE(16, 32, 1)
+    RAD_SHAPE_CASE(16, 16, 1)
+    RAD_SHAPE_CASE(16, 64, 2)
+    RAD_SHAPE_CASE(16, 32, 2)
+    RAD_SHAPE_CASE(16, 16, 2)
+    RAD_SHAPE_CASE(16, 64, 3)
+    RAD_SHAPE_CASE(16, 32, 3)
+    RAD_SHAPE_CASE(16, 16, 3)
 #undef RAD_SHAPE_CASE
     return hipErrorInvalidValue;
 }

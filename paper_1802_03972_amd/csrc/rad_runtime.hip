@@ -68,6 +68,17 @@ double shape_factor(int shape, double L, double omega)
     }
 }
 
+bool is_shape3(int shape) { return shape >= RAD_SHAPE_CIC3D && shape <= RAD_SHAPE_QSC3D; }
+
+// Cubic cell of side L: product over the axes of the 1-D shape factor at omega * n_c.
+double shape_factor3(int shape, double L, const double n[3], double omega)
+{
+    const int s1 = shape - RAD_SHAPE_CIC3D + RAD_SHAPE_CIC;
+    double g = 1.0;
+    for (int c = 0; c < 3; ++c) g *= shape_factor(s1, L, omega * std::fabs(n[c]));
+    return g;
+}
+
 // Orthonormal basis (e1, e2) of the plane normal to unit n.
 void normal_basis(const double n[3], double e1[3], double e2[3])
 {
@@ -127,6 +138,8 @@ struct rad_grid {
     int last_fold = -1;
     int* d_err = nullptr;
     double* d_out = nullptr;
+    float* d_g3 = nullptr;     // [n_dir][n_omega] for 3-D shapes
+    int variant = 0;           // rad::kVarDirect | rad::kVarShape3
     // kernel timing (rad_profile_*)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
@@ -140,7 +153,10 @@ namespace {
 // longer pushes are cut into several launches, each folded into the FP64 accumulator).
 constexpr int64_t kMaxPerWorkgroup = 32768;
 
-LaunchShape shape_of(const rad_tile& t) { return LaunchShape{t.w_per_lane, t.dir_per_wave, t.waves}; }
+LaunchShape shape_of(const rad_tile& t, int variant = 0)
+{
+    return LaunchShape{t.w_per_lane, t.dir_per_wave, t.waves, variant};
+}
 
 int tiles_d(const rad_grid* g) { return (g->n_dir + g->tile.dir_per_wave - 1) / g->tile.dir_per_wave; }
 int tiles_w(const rad_grid* g)
@@ -155,14 +171,14 @@ int max_splits(const rad_grid* g)
     return std::max(1, (target + nt - 1) / nt);
 }
 
-rad_tile default_tile(int n_dir, int n_omega)
+rad_tile default_tile(int n_dir, int n_omega, int variant = 0)
 {
     rad_tile t{};
     // Measured on the single-bunch grid (128 x 256): 64 directions per wave and 8 waves
     // (one 84 KB workgroup per CU) beats 32 x 4 waves (two per CU) by ~2%.
     t.dir_per_wave = n_dir <= 16 ? 16 : (n_dir < 48 ? 32 : 64);
     const int subs = 64 / t.dir_per_wave;
-    t.w_per_lane = n_omega >= 32 * subs ? 32 : 16;
+    t.w_per_lane = (n_omega >= 32 * subs && variant == 0) ? 32 : 16;
     const int per_wave = subs * t.w_per_lane;
     t.waves = std::min(8, std::max(1, (n_omega + per_wave - 1) / per_wave));
     // Two waves per SIMD (8 per CU) at ~160-256 VGPRs; LDS also bounds the count.
@@ -249,6 +265,7 @@ void free_grid(rad_grid* g)
     if (g->fold_stream) (void)hipStreamDestroy(g->fold_stream);
     if (g->d_err) (void)hipFree(g->d_err);
     if (g->d_out) (void)hipFree(g->d_out);
+    if (g->d_g3) (void)hipFree(g->d_g3);
     delete g;
 }
 
@@ -276,6 +293,7 @@ void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0,
     j.dirs9 = g->d_dirs9;
     j.omega = g->d_omega;
     j.gtab = g->d_gtab;
+    j.g3 = g->d_g3;
     j.domega = g->domega;
     j.n_dir = g->n_dir;
     j.n_omega = g->n_omega;
@@ -291,7 +309,7 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
 {
     int rc = ensure_partials(g);
     if (rc) return rc;
-    const LaunchShape ls = shape_of(g->tile);
+    const LaunchShape ls = shape_of(g->tile, g->variant);
     const int td = tiles_d(g), tw = tiles_w(g), nt = td * tw;
     const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;
     const int64_t target_splits = max_splits(g);   // <= part_splits (capacity may be larger)
@@ -380,9 +398,14 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     if (!out || !d) return fail(RAD_ERR_INVALID_ARG, "out and desc must be non-NULL");
     if (d->n_dir < 1 || !d->dirs) return fail(RAD_ERR_INVALID_ARG, "need n_dir >= 1 and dirs");
     if (d->n_omega < 1) return fail(RAD_ERR_INVALID_ARG, "need n_omega >= 1");
-    if (!(d->omega0 >= 0.0) || !std::isfinite(d->omega0) || !(d->domega >= 0.0) || !std::isfinite(d->domega))
+    if (d->omegas) {
+        for (int k = 0; k < d->n_omega; ++k)
+            if (!(d->omegas[k] >= 0.0) || !std::isfinite(d->omegas[k]))
+                return fail(RAD_ERR_INVALID_ARG, "omegas[%d] must be finite and >= 0", k);
+    } else if (!(d->omega0 >= 0.0) || !std::isfinite(d->omega0) || !(d->domega >= 0.0) || !std::isfinite(d->domega)) {
         return fail(RAD_ERR_INVALID_ARG, "omega0 and domega must be finite and >= 0");
-    if (d->shape < RAD_SHAPE_POINT || d->shape > RAD_SHAPE_GAUSS)
+    }
+    if (d->shape < RAD_SHAPE_POINT || d->shape > RAD_SHAPE_QSC3D)
         return fail(RAD_ERR_INVALID_ARG, "unknown shape %d", d->shape);
     if (d->shape != RAD_SHAPE_POINT && !(d->shape_len > 0.0 && std::isfinite(d->shape_len)))
         return fail(RAD_ERR_INVALID_ARG, "shape_len must be finite and > 0");
@@ -417,15 +440,28 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     g->cus = cus;
     const double q = kQe * d->dt;
     g->C = q * q / (16.0 * kPi * kPi * kPi * kEps0 * kC);
-    g->tile = default_tile(d->n_dir, d->n_omega);
+    g->variant = (d->omegas ? rad::kVarDirect : 0) | (is_shape3(d->shape) ? rad::kVarShape3 : 0);
+    if (d->omegas) g->domega = 0.0;
+    g->tile = default_tile(d->n_dir, d->n_omega, g->variant);
 
     std::vector<double> om((size_t)d->n_omega);
     std::vector<float2> gt((size_t)d->n_omega);
     for (int k = 0; k < d->n_omega; ++k) {
-        volatile double kd = (double)k * d->domega;  // one rounding per operation, no fma
-        om[k] = d->omega0 + kd;
-        const double gg = shape_factor(d->shape, d->shape_len, om[k]);
+        if (d->omegas) {
+            om[k] = d->omegas[k];
+        } else {
+            volatile double kd = (double)k * d->domega;  // one rounding per operation, no fma
+            om[k] = d->omega0 + kd;
+        }
+        const double gg = is_shape3(d->shape) ? 0.0 : shape_factor(d->shape, d->shape_len, om[k]);
         gt[k] = make_float2((float)gg, (float)(1.0 - gg));
+    }
+    std::vector<float> g3;
+    if (is_shape3(d->shape)) {
+        g3.resize((size_t)points);
+        for (int i = 0; i < d->n_dir; ++i)
+            for (int k = 0; k < d->n_omega; ++k)
+                g3[(size_t)i * d->n_omega + k] = (float)shape_factor3(d->shape, d->shape_len, d->dirs + 3 * i, om[k]);
     }
 
     DeviceGuard dg(g->device);
@@ -435,7 +471,8 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
         hipMalloc(&g->d_gtab, gt.size() * sizeof(float2)) != hipSuccess ||
         hipMalloc(&g->d_S, sbytes) != hipSuccess ||
         hipMalloc(&g->d_err, sizeof(int)) != hipSuccess ||
-        hipMalloc(&g->d_out, (size_t)points * 6 * sizeof(double)) != hipSuccess) {
+        hipMalloc(&g->d_out, (size_t)points * 6 * sizeof(double)) != hipSuccess ||
+        (!g3.empty() && hipMalloc(&g->d_g3, g3.size() * sizeof(float)) != hipSuccess)) {
         free_grid(g);
         return fail(RAD_ERR_OOM, "device allocation failed for a %lld-point grid", (long long)points);
     }
@@ -453,6 +490,7 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     if ((e = hipMemcpy(g->d_dirs9, dirs9.data(), dirs9.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(g->d_omega, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(g->d_gtab, gt.data(), gt.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+        (!g3.empty() && (e = hipMemcpy(g->d_g3, g3.data(), g3.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) ||
         (e = rad::launch_fill(g->d_S, points * 4, 0.0, nullptr)) != hipSuccess ||
         (e = rad::launch_fill_int(g->d_err, 1, 0, nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
@@ -602,6 +640,8 @@ int rad_set_tile(rad_grid* g, const rad_tile* t)
     if (!g || !t) return fail(RAD_ERR_INVALID_ARG, "grid and tile must be non-NULL");
     int rc = validate_tile(*t);
     if (rc) return rc;
+    if (g->variant != 0 && t->w_per_lane != 16)
+        return fail(RAD_ERR_INVALID_ARG, "grids with a frequency list or a 3-D shape need w_per_lane = 16");
     DeviceGuard dg(g->device);
     const rad_tile old = g->tile;
     g->tile = *t;
@@ -879,6 +919,8 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         }
         if (itm.p.dtype != dtype) return fail(RAD_ERR_INVALID_ARG, "item %d: particle dtype differs within the batch", i);
         if (itm.grid->precision != g0->precision) return fail(RAD_ERR_INVALID_ARG, "item %d: precision mode differs", i);
+        if (itm.grid->variant != g0->variant)
+            return fail(RAD_ERR_INVALID_ARG, "item %d: frequency-list / 3-D-shape kind differs within the batch", i);
         ItemInfo in;
         in.grid = itm.grid;
         in.job.i_begin = 0;
@@ -890,7 +932,9 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         items_p.push_back(&itm.p);
     }
     if (info.empty()) return RAD_OK;
-    const rad_tile btile = b->tile_set ? b->tile : default_tile(g0->n_dir, g0->n_omega);
+    const rad_tile btile = b->tile_set ? b->tile : default_tile(g0->n_dir, g0->n_omega, g0->variant);
+    if (g0->variant != 0 && btile.w_per_lane != 16)
+        return fail(RAD_ERR_INVALID_ARG, "batches of grids with a frequency list or a 3-D shape need w_per_lane = 16");
     for (size_t i = 0; i < info.size(); ++i) {
         ItemInfo& in = info[i];
         const int64_t i_end = in.job.i_end, nps = in.job.n_per_step;
@@ -916,7 +960,7 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         in.iter_begin = I;
         I += in.iters;
     }
-    const LaunchShape ls = shape_of(btile);
+    const LaunchShape ls = shape_of(btile, g0->variant);
     const int TD = rad::tile_dirs(ls), TO = rad::tile_omegas(ls);
     const int R_target = std::max(1, b->cus * btile.wg_per_cu);
     const int64_t per_launch = (int64_t)R_target * (kMaxPerWorkgroup / rad::kChunk);
@@ -995,7 +1039,8 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         const int32_t* d_list = reinterpret_cast<const int32_t*>(sl.dev + o_list);
         hipGraphExec_t exec = nullptr;
         if (use_graph) {
-            const BatchGraphKey key{dtype, g0->precision, ls.w_per_lane, ls.dir_per_wave, ls.waves, R_launch, slot_index};
+            const BatchGraphKey key{dtype, g0->precision * 16 + ls.variant, ls.w_per_lane, ls.dir_per_wave, ls.waves,
+                                    R_launch, slot_index};
             for (auto& ge : b->graphs)
                 if (ge.key == key && ge.gen == b->graph_gen) exec = ge.exec;
             if (!exec) {

@@ -29,6 +29,7 @@ MUTANTS = {
     "beta_dot_n_transposed": ("double D = 1.0 - (beta[0] * n[0] + beta[1] * n[1] + beta[2] * n[2]);",
                               "double D = 1.0 - (beta[0] * n[0] + beta[1] * n[2] + beta[2] * n[1]);"),
     "phase_cos_sin_swapped": ("double cr = cos(phase), ci = sin(phase);", "double cr = sin(phase), ci = cos(phase);"),
+    "cubic_cell_drops_an_axis": ("oracle_shape_g(base, len, omega * fabs(n[1])) *", "1.0 *"),
 }
 
 

@@ -301,3 +301,39 @@ def test_empty_and_zero_weight(orc):
     assert np.all(oracle.spectrum(empty, dirs, om, "cic", 1e-7, w.dt) == 0.0)
     s0 = dict(s); s0["w"] = np.zeros_like(s["w"])
     assert np.all(oracle.spectrum(s0, dirs, om, "cic", 1e-7, w.dt) == 0.0)
+
+
+# --------------------------------------------------------------------------- cubic-cell shapes
+@pytest.mark.parametrize("shape", ["cic3d", "tsc3d", "qsc3d"])
+def test_cubic_cell_form_factor_monte_carlo(orc, shape):
+    """Eq. 10 by Monte Carlo for electrons filling a cubic cell (each axis from the 1-D
+    density), observed along tilted directions, vs N + (N^2 - N) g(n, omega)."""
+    rng = np.random.default_rng(77)
+    N, R, L = 12, 120_000, 0.1e-6
+    offs = np_oracle.sample_offsets3(rng, shape, L, (R, N))
+    for n in (np.array([0.6, 0.0, 0.8]), np.array([0.48, 0.6, 0.64]), np.array([0.0, 0.0, 1.0])):
+        for omega in (2e15, 6e15, 1.5e16):
+            x = np_oracle.electron_phase_sum3(offs, n, omega)
+            mean, err = x.mean(), x.std() / np.sqrt(R)
+            ref = oracle.form_factor_sq(N, oracle.shape_g3(shape, L, n, omega))
+            assert abs(mean - ref) <= 4.5 * err + 1e-9 * ref, (shape, n, omega, mean, ref, err)
+
+
+def test_cubic_cell_reduces_to_1d_along_an_axis(orc):
+    for base in ("cic", "tsc", "qsc"):
+        for omega in (0.0, 3e15, 1e16, 4e16):
+            for axis in range(3):
+                n = np.zeros(3); n[axis] = 1.0
+                assert oracle.shape_g3(base + "3d", 1e-7, n, omega) == pytest.approx(
+                    oracle.shape_g(base, 1e-7, omega), rel=1e-14, abs=1e-300)
+                assert float(np_oracle.shape_g3(base + "3d", 1e-7, n, omega)) == pytest.approx(
+                    oracle.shape_g(base, 1e-7, omega), rel=1e-13, abs=1e-300)
+
+
+def test_cubic_cell_spectrum_c_vs_numpy_oracle(orc):
+    w, s = tiny_samples(n=128, steps=8, seed=1)
+    dirs = np.array([[0.3, 0.4, np.sqrt(0.75)], [0.0, 0.0, 1.0], [0.6, 0.0, 0.8]])
+    om = np.linspace(0, 4e16, 9)
+    Ic = oracle.spectrum(s, dirs, om, "cic3d", 0.1e-6, w.dt)
+    In = np_oracle.spectrum(s, dirs, om, "cic3d", 0.1e-6, w.dt)
+    assert np.max(np.abs(Ic - In)) <= 1e-12 * np.max(In)
