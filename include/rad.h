@@ -295,6 +295,33 @@ int rad_server_counters_read(rad_server* s, rad_server_counters* out);
 /* Drain, stop the scheduler thread and free the server (not its grids). */
 int rad_server_destroy(rad_server* s);
 
+/* ---- post-processing variant: tracked particles -------------------------------- */
+
+/* For a small set of tracked particles (same particles, same order, every step) the
+ * device keeps each particle's own time integral T_m(n, omega) = sum_j A_{j,m}(n) chi_{j,m}
+ * in FP64 (n_particles x n_dir x n_omega x 2 complex numbers), and the form factor is
+ * applied only when the spectrum is read (the post-processing alternative of Sec. 3.3):
+ *   I = C | sum_m F_m(omega) T_m(n, omega) |^2,  F_m = sqrt(N_m + (N_m^2 - N_m) g).
+ * With constant weights this equals the in-situ sum; weights and shape may be changed
+ * between read-outs without recomputing.  Memory grows with the number of particles,
+ * which is why this is meant for test-particle sets only. */
+typedef struct rad_tracked rad_tracked;
+
+/* Grid fields of `d` (directions, frequencies or frequency list, dt, device) are used;
+ * the shape fields are ignored (chosen at read-out); precision must be RAD_PHASE_F64. */
+int rad_tracked_create(rad_tracked** out, const rad_grid_desc* d, int64_t n_particles);
+int rad_tracked_destroy(rad_tracked* tr);
+int rad_tracked_reset(rad_tracked* tr, void* stream);
+
+/* One step at time t; device arrays of n_particles elements (the weight field is not
+ * read and may be NULL).  Stream-ordered; data errors set the sticky flag reported at read-out. */
+int rad_tracked_push_step(rad_tracked* tr, double t, const rad_particles* p, void* stream);
+
+/* Spectrum with the given HOST weights (n_particles, >= 0) and shape applied now;
+ * I_host: n_dir x n_omega doubles.  Synchronises `stream`. */
+int rad_tracked_spectrum(rad_tracked* tr, const double* weights_host, int32_t shape, double shape_len,
+                         double* I_host, void* stream);
+
 /* Library and device facts: compute-unit count of `device`, or a negative code. */
 int rad_device_cus(int32_t device);
 

@@ -359,6 +359,57 @@ class Server:
         return {k: getattr(c, k) for k, _ in _lib.ServerCounters._fields_}
 
 
+class Tracked:
+    """Post-processing variant for a small set of tracked particles: per-particle time
+    integrals on the device, form factor (weights and shape) applied at read-out."""
+
+    def __init__(self, dirs, omega0: float, domega: float, n_omega: int, n_particles: int,
+                 dt: float = 5e-17, device: int = 0, omegas=None):
+        self._dirs = np.ascontiguousarray(dirs, np.float64).reshape(-1, 3)
+        self._omegas = None if omegas is None else np.ascontiguousarray(omegas, np.float64).reshape(-1)
+        if self._omegas is not None:
+            n_omega = self._omegas.size
+        self.n_dir, self.n_omega, self.n_particles = int(self._dirs.shape[0]), int(n_omega), int(n_particles)
+        self.device = int(device)
+        desc = _lib.GridDesc(self.n_dir, self._dirs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             float(omega0), float(domega), self.n_omega, 0, 0.0, float(dt), PHASE_F64,
+                             self.device, None if self._omegas is None else
+                             self._omegas.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().rad_tracked_create(ctypes.byref(h), ctypes.byref(desc), self.n_particles))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.check(_lib.lib().rad_tracked_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None) -> None:
+        _lib.check(_lib.lib().rad_tracked_reset(self._h, _stream_handle(stream, self.device)))
+
+    def push_step(self, t: float, particles: dict, stream=None) -> None:
+        p, n, keep = make_particles(particles, expect_len=self.n_particles, device=self.device)
+        _lib.check(_lib.lib().rad_tracked_push_step(self._h, float(t), ctypes.byref(p),
+                                                    _stream_handle(stream, self.device)))
+
+    def spectrum(self, weights, shape="cic", shape_len: float = 1e-7, stream=None) -> np.ndarray:
+        w = np.ascontiguousarray(weights, np.float64).reshape(-1)
+        if w.size != self.n_particles:
+            raise ValueError(f"need {self.n_particles} weights")
+        out = np.empty((self.n_dir, self.n_omega), np.float64)
+        sid = SHAPES[shape] if isinstance(shape, str) else int(shape)
+        _lib.check(_lib.lib().rad_tracked_spectrum(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sid,
+                                                   float(shape_len), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                   _stream_handle(stream, self.device)))
+        return out
+
+
 def device_cus(device: int = 0) -> int:
     rc = _lib.lib().rad_device_cus(int(device))
     if rc < 0:

@@ -114,6 +114,11 @@ SIGNATURES = {
     "rad_server_drain": (ctypes.c_int, [_vp]),
     "rad_server_counters_read": (ctypes.c_int, [_vp, ctypes.POINTER(ServerCounters)]),
     "rad_server_destroy": (ctypes.c_int, [_vp]),
+    "rad_tracked_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GridDesc), ctypes.c_int64]),
+    "rad_tracked_destroy": (ctypes.c_int, [_vp]),
+    "rad_tracked_reset": (ctypes.c_int, [_vp, _vp]),
+    "rad_tracked_push_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(Particles), _vp]),
+    "rad_tracked_spectrum": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _dp, _vp]),
     "rad_debug_trig_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
 }
 

@@ -56,6 +56,19 @@ struct FoldJob {
     int32_t list_begin, list_end;   // into the segment index list
 };
 
+// Post-processing variant: one step of tracked particles into per-particle integrals.
+struct TrackedArgs {
+    const void* f[10];      // x, y, z, bx, by, bz, dbx, dby, dbz, w (w is not used)
+    int64_t n_particles;
+    double t;
+    const double* dirs9;
+    const double* omega;
+    double domega;
+    double* T;              // [n_particles][n_omega][n_dir][4] FP64
+    int* err;
+    int32_t n_dir, n_omega;
+};
+
 struct LaunchShape {
     int w_per_lane;    // 16 | 32 (16 only for variant != 0)
     int dir_per_wave;  // 16 | 32 | 64
@@ -94,5 +107,9 @@ hipError_t launch_cartesian(const double* S, const double* dirs9, double* out, i
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 hipError_t launch_trig_probe(const float* in, float* out, int n, hipStream_t st);
+hipError_t launch_tracked_accumulate(const TrackedArgs& a, int dtype, bool direct, hipStream_t st);
+hipError_t launch_tracked_finalize(const double* T, const double* wts, const double* gk, const double* g3,
+                                   int64_t n_particles, int n_dir, int n_omega, double C, double* I,
+                                   hipStream_t st);
 
 }  // namespace rad

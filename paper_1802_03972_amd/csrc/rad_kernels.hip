@@ -67,13 +67,12 @@ __device__ __forceinline__ double load_wide(const void* p, int64_t i)
 
 // Per (particle, direction) geometry.  Writes A1, A2 (FP32), w = exp(i domega tau) and
 // tau/(2 pi) (FP64).
-template <int PREC, bool WANT_W>
+template <int PREC, bool WANT_W, int P = kChunk>
 __device__ __forceinline__ void particle_direction_setup(const double* __restrict__ raw, int m,
                                                          const double* __restrict__ dv,
                                                          double domega, float4& geo,
                                                          double& ph_out, int* err)
 {
-    constexpr int P = kChunk;
     const double x = raw[0 * P + m], y = raw[1 * P + m], z = raw[2 * P + m];
     const double bx = raw[3 * P + m], by = raw[4 * P + m], bz = raw[5 * P + m];
     const double dbx = raw[6 * P + m], dby = raw[7 * P + m], dbz = raw[8 * P + m];
@@ -368,6 +367,81 @@ __global__ void __launch_bounds__(512) k_accumulate_batch(const Job* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Post-processing variant: tracked particles keep their own time integral
+// T_m(n, omega) = sum_j A_{j,m}(n) exp(i omega tau_{j,m}) (no form factor) in FP64,
+// layout [m][omega][dir][4]; the form factor is applied only when the spectrum is read.
+// One thread per (particle, direction, block of W frequencies); geometry in FP64 as in the
+// main path; the block's frequencies follow the same rotation recurrence (or, for explicit
+// frequency lists, the per-term FP64 phase).
+// ---------------------------------------------------------------------------------------
+template <typename InT, bool DIRECT>
+__global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
+{
+    constexpr int W = 16;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_blocks = (a.n_omega + W - 1) / W;
+    const int d = (int)(idx % a.n_dir);
+    const int64_t rest = idx / a.n_dir;
+    const int ob = (int)(rest % n_blocks);
+    const int64_t m = rest / n_blocks;
+    if (m >= a.n_particles) return;
+    double raw[11];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) raw[f] = load_wide<InT>(a.f[f], m);
+    raw[9] = 1.0;      // weights enter only at read-out; the weight field is never read
+    raw[10] = a.t;
+    float4 gv;
+    double ph;
+    particle_direction_setup<0, !DIRECT, 1>(raw, 0, a.dirs9 + 9 * d, a.domega, gv, ph, a.err);
+    const int o0 = ob * W;
+    float zr = 1.f, zi = 0.f;
+    if constexpr (!DIRECT) {
+        double rv = a.omega[o0] * ph;
+        rv -= floor(rv);
+        sincos_rev_fast(static_cast<float>(rv), zi, zr);
+    }
+    double* T = a.T + ((m * a.n_omega + o0) * a.n_dir + d) * 4;
+    for (int k = 0; k < W && o0 + k < a.n_omega; ++k, T += (int64_t)a.n_dir * 4) {
+        if constexpr (DIRECT) {
+            double rv = a.omega[o0 + k] * ph;
+            rv -= floor(rv);
+            sincos_rev_fast(static_cast<float>(rv), zi, zr);
+        }
+        T[0] += (double)(gv.x * zr);
+        T[1] += (double)(gv.x * zi);
+        T[2] += (double)(gv.y * zr);
+        T[3] += (double)(gv.y * zi);
+        if constexpr (!DIRECT) {
+            const float nr = fmaf(zr, gv.z, -(zi * gv.w));
+            const float ni = fmaf(zr, gv.w, zi * gv.z);
+            zr = nr;
+            zi = ni;
+        }
+    }
+}
+
+// I[d][k] = C |sum_m F_m(d, k) T_m(k, d)|^2 with F_m = sqrt(N_m + (N_m^2 - N_m) g) in FP64;
+// g from gk[k] (1-D shape) or g3[d][k] (3-D shape).
+__global__ void k_tracked_finalize(const double* __restrict__ T, const double* __restrict__ wts,
+                                   const double* __restrict__ gk, const double* __restrict__ g3,
+                                   int64_t n_particles, int n_dir, int n_omega, double C,
+                                   double* __restrict__ I)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_dir * n_omega) return;
+    const int d = (int)(i / n_omega), k = (int)(i % n_omega);
+    const double g = g3 ? g3[(int64_t)d * n_omega + k] : gk[k];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int64_t m = 0; m < n_particles; ++m) {
+        const double N = wts[m];
+        const double F = sqrt(fmax(N + (N * N - N) * g, 0.0));
+        const double* t = T + ((m * n_omega + k) * n_dir + d) * 4;
+        s0 += F * t[0]; s1 += F * t[1]; s2 += F * t[2]; s3 += F * t[3];
+    }
+    I[i] = C * (s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3);
+}
+
 // S[i] += sum over splits of part[s][i], in split order, in FP64.
 __global__ void k_fold(const float* __restrict__ part, double* __restrict__ S, int splits,
                        int64_t count)
@@ -612,6 +686,32 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_int, dim3(grid1d(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_tracked_accumulate(const TrackedArgs& a, int dtype, bool direct, hipStream_t st)
+{
+    const int64_t n_blocks = (a.n_omega + 15) / 16;
+    const int64_t threads = a.n_particles * n_blocks * a.n_dir;
+    if (threads <= 0) return hipSuccess;
+    const dim3 grid(grid1d(threads, 256));
+    if (dtype == 0) {
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<float, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<float, false>), grid, dim3(256), 0, st, a);
+    } else {
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<double, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<double, false>), grid, dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tracked_finalize(const double* T, const double* wts, const double* gk, const double* g3,
+                                   int64_t n_particles, int n_dir, int n_omega, double C, double* I,
+                                   hipStream_t st)
+{
+    const int64_t n = (int64_t)n_dir * n_omega;
+    hipLaunchKernelGGL(k_tracked_finalize, dim3(grid1d(n, 256)), dim3(256), 0, st, T, wts, gk, g3, n_particles,
+                       n_dir, n_omega, C, I);
     return hipGetLastError();
 }
 

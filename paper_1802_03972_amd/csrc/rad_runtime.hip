@@ -1196,3 +1196,169 @@ extern "C" int rad_batcher_get_tile(rad_batcher* b, rad_tile* t)
     *t = b->tile;
     return RAD_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// Post-processing variant: tracked particles with per-particle time integrals.
+// ---------------------------------------------------------------------------------------
+struct rad_tracked {
+    int device = 0;
+    int64_t n_particles = 0;
+    int n_dir = 0, n_omega = 0;
+    double domega = 0, dt = 0, C = 0;
+    bool direct = false;
+    std::vector<double> dirs, om;
+    double* d_dirs9 = nullptr;
+    double* d_omega = nullptr;
+    double* d_T = nullptr;
+    double* d_w = nullptr;
+    double* d_g = nullptr;     // n_dir * n_omega shape factors of the last read-out
+    double* d_I = nullptr;
+    int* d_err = nullptr;
+};
+
+namespace {
+
+void free_tracked(rad_tracked* tr)
+{
+    if (!tr) return;
+    DeviceGuard dg(tr->device);
+    for (double* p : {tr->d_dirs9, tr->d_omega, tr->d_T, tr->d_w, tr->d_g, tr->d_I})
+        if (p) (void)hipFree(p);
+    if (tr->d_err) (void)hipFree(tr->d_err);
+    delete tr;
+}
+
+}  // namespace
+
+extern "C" int rad_tracked_create(rad_tracked** out, const rad_grid_desc* d, int64_t n_particles)
+{
+    if (!out || !d) return fail(RAD_ERR_INVALID_ARG, "out and desc must be non-NULL");
+    if (n_particles < 1) return fail(RAD_ERR_INVALID_ARG, "need n_particles >= 1");
+    if (d->precision != RAD_PHASE_F64) return fail(RAD_ERR_INVALID_ARG, "tracked particles use the FP64-phase mode");
+    // reuse the grid validation (directions, frequencies, dt) with a neutral shape
+    rad_grid_desc chk = *d;
+    chk.shape = RAD_SHAPE_POINT;
+    rad_grid* probe = nullptr;
+    int rc = rad_create_grid(&probe, &chk);
+    if (rc) return rc;
+    rad_tracked* tr = new rad_tracked;
+    tr->device = d->device;
+    tr->n_particles = n_particles;
+    tr->n_dir = d->n_dir;
+    tr->n_omega = d->n_omega;
+    tr->domega = probe->domega;
+    tr->dt = d->dt;
+    tr->C = probe->C;
+    tr->direct = (probe->variant & rad::kVarDirect) != 0;
+    tr->dirs.assign(d->dirs, d->dirs + 3 * (size_t)d->n_dir);
+    tr->om.resize((size_t)d->n_omega);
+    DeviceGuard dg(d->device);
+    const int64_t points = (int64_t)d->n_dir * d->n_omega;
+    const size_t tbytes = (size_t)n_particles * points * 4 * sizeof(double);
+    if (hipMalloc(&tr->d_dirs9, (size_t)d->n_dir * 9 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_omega, (size_t)d->n_omega * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_T, tbytes) != hipSuccess ||
+        hipMalloc(&tr->d_w, (size_t)n_particles * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_g, (size_t)points * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_I, (size_t)points * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_err, sizeof(int)) != hipSuccess) {
+        rad_destroy_grid(probe);
+        free_tracked(tr);
+        return fail(RAD_ERR_OOM, "cannot allocate %zu B of per-particle integrals", tbytes);
+    }
+    hipError_t e;
+    if ((e = hipMemcpy(tr->d_dirs9, probe->d_dirs9, (size_t)d->n_dir * 9 * sizeof(double), hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy(tr->d_omega, probe->d_omega, (size_t)d->n_omega * sizeof(double), hipMemcpyDeviceToDevice)) != hipSuccess ||
+        (e = hipMemcpy(tr->om.data(), probe->d_omega, (size_t)d->n_omega * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = rad::launch_fill(tr->d_T, (int64_t)(tbytes / sizeof(double)), 0.0, nullptr)) != hipSuccess ||
+        (e = rad::launch_fill_int(tr->d_err, 1, 0, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        rad_destroy_grid(probe);
+        free_tracked(tr);
+        return hip_fail(e, "tracked initialisation");
+    }
+    rad_destroy_grid(probe);
+    *out = tr;
+    return RAD_OK;
+}
+
+extern "C" int rad_tracked_destroy(rad_tracked* tr)
+{
+    if (!tr) return RAD_OK;
+    {
+        DeviceGuard dg(tr->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_tracked(tr);
+    return RAD_OK;
+}
+
+extern "C" int rad_tracked_reset(rad_tracked* tr, void* stream)
+{
+    if (!tr) return fail(RAD_ERR_INVALID_ARG, "tracked is NULL");
+    DeviceGuard dg(tr->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = rad::launch_fill(tr->d_T, tr->n_particles * tr->n_dir * tr->n_omega * 4, 0.0, st);
+    if (e == hipSuccess) e = rad::launch_fill_int(tr->d_err, 1, 0, st);
+    if (e != hipSuccess) return hip_fail(e, "tracked reset");
+    return RAD_OK;
+}
+
+extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_particles* p, void* stream)
+{
+    if (!tr) return fail(RAD_ERR_INVALID_ARG, "tracked is NULL");
+    if (!std::isfinite(t)) return fail(RAD_ERR_INVALID_ARG, "t is not finite");
+    if (!p) return fail(RAD_ERR_INVALID_ARG, "particles is NULL");
+    rad_particles q = *p;
+    if (!q.w) q.w = q.x;   // the weight field is not read here
+    int rc = check_particles(&q);
+    if (rc) return rc;
+    DeviceGuard dg(tr->device);
+    rad::TrackedArgs a{};
+    a.f[0] = p->x; a.f[1] = p->y; a.f[2] = p->z;
+    a.f[3] = p->bx; a.f[4] = p->by; a.f[5] = p->bz;
+    a.f[6] = p->dbx; a.f[7] = p->dby; a.f[8] = p->dbz; a.f[9] = nullptr;
+    a.n_particles = tr->n_particles;
+    a.t = t;
+    a.dirs9 = tr->d_dirs9;
+    a.omega = tr->d_omega;
+    a.domega = tr->domega;
+    a.T = tr->d_T;
+    a.err = tr->d_err;
+    a.n_dir = tr->n_dir;
+    a.n_omega = tr->n_omega;
+    hipError_t e = rad::launch_tracked_accumulate(a, p->dtype, tr->direct, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "tracked accumulate launch");
+    return RAD_OK;
+}
+
+extern "C" int rad_tracked_spectrum(rad_tracked* tr, const double* weights_host, int32_t shape, double shape_len,
+                                    double* I_host, void* stream)
+{
+    if (!tr || !weights_host || !I_host) return fail(RAD_ERR_INVALID_ARG, "NULL argument");
+    if (shape < RAD_SHAPE_POINT || shape > RAD_SHAPE_QSC3D) return fail(RAD_ERR_INVALID_ARG, "unknown shape %d", shape);
+    if (shape != RAD_SHAPE_POINT && !(shape_len > 0.0 && std::isfinite(shape_len)))
+        return fail(RAD_ERR_INVALID_ARG, "shape_len must be finite and > 0");
+    for (int64_t m = 0; m < tr->n_particles; ++m)
+        if (!(weights_host[m] >= 0.0) || !std::isfinite(weights_host[m]))
+            return fail(RAD_ERR_INVALID_ARG, "weight %lld must be finite and >= 0", (long long)m);
+    DeviceGuard dg(tr->device);
+    hipStream_t st = (hipStream_t)stream;
+    const bool s3 = is_shape3(shape);
+    std::vector<double> g(s3 ? (size_t)tr->n_dir * tr->n_omega : (size_t)tr->n_omega);
+    for (int d = 0; d < (s3 ? tr->n_dir : 1); ++d)
+        for (int k = 0; k < tr->n_omega; ++k)
+            g[(size_t)d * tr->n_omega + k] = s3 ? shape_factor3(shape, shape_len, tr->dirs.data() + 3 * d, tr->om[k])
+                                                : shape_factor(shape, shape_len, tr->om[k]);
+    RAD_HIP(hipMemcpyAsync(tr->d_g, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    RAD_HIP(hipMemcpyAsync(tr->d_w, weights_host, (size_t)tr->n_particles * sizeof(double), hipMemcpyHostToDevice, st));
+    hipError_t e = rad::launch_tracked_finalize(tr->d_T, tr->d_w, s3 ? nullptr : tr->d_g, s3 ? tr->d_g : nullptr,
+                                                tr->n_particles, tr->n_dir, tr->n_omega, tr->C, tr->d_I, st);
+    if (e != hipSuccess) return hip_fail(e, "tracked finalize launch");
+    int flag = 0;
+    RAD_HIP(hipMemcpyAsync(&flag, tr->d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+    RAD_HIP(hipStreamSynchronize(st));
+    if (flag) return fail(RAD_ERR_BAD_DATA, "device detected invalid particle data");
+    RAD_HIP(hipMemcpyAsync(I_host, tr->d_I, (size_t)tr->n_dir * tr->n_omega * sizeof(double), hipMemcpyDeviceToHost, st));
+    RAD_HIP(hipStreamSynchronize(st));
+    return RAD_OK;
+}

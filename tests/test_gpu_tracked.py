@@ -1,0 +1,118 @@
+"""Post-processing variant (tracked particles) through the C ABI: per-particle time
+integrals on the device with the form factor applied at read-out.  With constant weights it
+equals the in-situ sum; shape and weights can be changed after the run."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import SINGLE, flatten
+from tests.helpers import e_inf, to_device, step_slice
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rad():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1802_03972_amd as rad
+    rad._lib.lib()
+    return rad
+
+
+def run_tracked(rad, w, st, dtype="f32", omegas=None):
+    tr = rad.Tracked(w.directions(), w.omega0, w.domega, w.n_omega, w.n_particles, dt=w.dt, omegas=omegas)
+    dev = to_device(st, dtype)
+    for j, t in enumerate(w.times()):
+        tr.push_step(float(t), step_slice(dev, j, w.n_particles))
+    return tr
+
+
+def with_weights(st, wts):
+    out = dict(st)
+    out["w"] = np.broadcast_to(np.asarray(wts, np.float64)[None, :], st["w"].shape).copy()
+    return out
+
+
+def test_tracked_equals_in_situ_and_oracle(rad):
+    w = SINGLE.scaled(n_particles=900, n_steps=4, nx_dir=4, ny_dir=8, n_omega=160, seed=41)
+    st = w.steps()
+    assert np.all(st["w"] == st["w"][0:1])          # constant weights along the run
+    tr = run_tracked(rad, w, st)
+    I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
+    g = rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape, shape_len=w.shape_len, dt=w.dt)
+    g.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
+    e_grid, e_or = e_inf(I, g.spectrum()), e_inf(I, Iref)
+    print(f"tracked vs in-situ {e_grid:.3e}, vs oracle {e_or:.3e}")
+    assert e_grid <= 1e-5 and e_or <= TOL
+
+
+@pytest.mark.parametrize("shape", ["point", "tsc", "gauss", "qsc3d"])
+def test_shape_chosen_after_the_run(rad, shape):
+    """One run, read out with a shape other than the one the workload names."""
+    w = SINGLE.scaled(n_particles=500, n_steps=3, nx_dir=4, ny_dir=4, n_omega=96, seed=42)
+    st = w.steps()
+    tr = run_tracked(rad, w, st, dtype="f64")
+    I = tr.spectrum(st["w"][0], shape, w.shape_len)
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), shape, w.shape_len, w.dt)
+    err = e_inf(I, Iref)
+    print(f"post-hoc shape {shape}: e_inf {err:.3e}")
+    assert err <= TOL
+
+
+def test_weights_chosen_after_the_run(rad):
+    w = SINGLE.scaled(n_particles=400, n_steps=3, nx_dir=4, ny_dir=4, n_omega=64, seed=43)
+    st = w.steps()
+    tr = run_tracked(rad, w, st)
+    wts = np.random.default_rng(7).uniform(0.0, 5e4, w.n_particles)
+    wts[::17] = 0.0
+    I = tr.spectrum(wts, w.shape, w.shape_len)
+    Iref = oracle.spectrum(flatten(with_weights(st, wts), w.times()), w.directions(), w.omegas(), w.shape,
+                           w.shape_len, w.dt)
+    assert e_inf(I, Iref) <= TOL
+
+
+def test_log_spaced_frequencies(rad):
+    w = SINGLE.scaled(n_particles=300, n_steps=3, nx_dir=4, ny_dir=4, seed=44)
+    st = w.steps()
+    om = np.geomspace(1e13, 2e19, 70)
+    tr = run_tracked(rad, w, st, omegas=om)
+    I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
+    col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
+    assert e_inf(I, Iref) <= TOL and col.max() <= TOL
+
+
+def test_reset_and_repeat_is_bitwise(rad):
+    w = SINGLE.scaled(n_particles=200, n_steps=2, nx_dir=2, ny_dir=4, n_omega=40, seed=45)
+    st = w.steps()
+    tr = run_tracked(rad, w, st)
+    I1 = tr.spectrum(st["w"][0], "cic", w.shape_len)
+    tr.reset()
+    dev = to_device(st, "f32")
+    for j, t in enumerate(w.times()):
+        tr.push_step(float(t), step_slice(dev, j, w.n_particles))
+    I2 = tr.spectrum(st["w"][0], "cic", w.shape_len)
+    assert np.array_equal(I1, I2)
+
+
+def test_errors(rad):
+    w = SINGLE.scaled(n_particles=64, n_steps=1, nx_dir=2, ny_dir=2, n_omega=32, seed=46)
+    st = w.steps()
+    tr = run_tracked(rad, w, st)
+    with pytest.raises(rad.RadError) as ei:
+        tr.spectrum(-np.ones(w.n_particles), "cic", w.shape_len)
+    assert ei.value.code == rad.RAD_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        tr.spectrum(np.ones(w.n_particles + 1), "cic", w.shape_len)
+    bad = dict(st)
+    bad["bz"] = st["bz"].copy()
+    bad["bz"][0, 3] = 2.0                              # |beta| > 1: 1 - beta.n < 0
+    tr.reset()
+    tr.push_step(float(w.times()[0]), step_slice(to_device(bad, "f32"), 0, w.n_particles))
+    with pytest.raises(rad.RadError) as ei:
+        tr.spectrum(st["w"][0], "cic", w.shape_len)
+    assert ei.value.code == rad.RAD_ERR_BAD_DATA
