@@ -44,6 +44,11 @@ def parse():
                     help="batched_uneven: distinct generated steps per bunch, cycled over its 200 steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-pushes", type=int, default=100)
+    ap.add_argument("--omega-grid", choices=("uniform", "log"), default="uniform",
+                    help="single_bunch_fp32: 'log' passes the frequencies as an explicit log-spaced list "
+                         "(1e-4 * omega_max .. omega_max), evaluated with a per-term FP64 phase")
+    ap.add_argument("--shape", default="", help="single_bunch_fp32: override the macro-particle shape "
+                                                "(e.g. cic3d for the direction-dependent cubic cell)")
     ap.add_argument("--tile", default="", help="override launch shape: w_per_lane,dir_per_wave,waves,wg_per_cu")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming kernel (read MIB, write MIB) to scale HBM byte counters")
@@ -118,6 +123,12 @@ def main() -> int:
         return bench_fig3(args)
 
     w = SINGLE if args.workload == "single_bunch_fp32" else TINY
+    if args.shape:
+        w = w.scaled(shape=args.shape)
+    om_list = np.geomspace(1e-4 * w.omega_max, w.omega_max, w.n_omega) if args.omega_grid == "log" else None
+    omegas = om_list if om_list is not None else w.omegas()
+    variant = bool(args.shape) or om_list is not None
+    big = args.workload == "single_bunch_fp32"
     dev_id = 0
     torch.cuda.set_device(dev_id)
     stream = torch.cuda.current_stream(dev_id)
@@ -136,7 +147,7 @@ def main() -> int:
     slices = [{k: v[j * n:(j + 1) * n] for k, v in dev.items()} for j in range(w.n_steps)]
 
     g = rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape,
-                 shape_len=w.shape_len, dt=w.dt, device=dev_id)
+                 shape_len=w.shape_len, dt=w.dt, device=dev_id, omegas=om_list)
     if args.tile:
         a, b, c, d = (int(x) for x in args.tile.split(","))
         g.set_tile(w_per_lane=a, dir_per_wave=b, waves=c, wg_per_cu=d)
@@ -179,7 +190,8 @@ def main() -> int:
     achieved = upd_per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md", tile) if w is SINGLE else None,
+                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md", tile)
+                if big and not variant else None,
                 "traffic_source": "profiles/k_accumulate_single_bunch_fp32.md (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, bytes per launch)",
                 "kernel": "k_accumulate", "avg_launch_ms": round(avg_ms, 4),
                 "updates_per_launch": int(upd_per_launch), "flops_per_update": FLOPS_PER_UPDATE,
@@ -208,13 +220,13 @@ def main() -> int:
         import oracle
         cores = len(os.sched_getaffinity(0))
         oracle.set_threads(cores)
-        ns, kw = (4, 4) if w is SINGLE else (w.n_steps, 1)
+        ns, kw = (4, 4) if big else (w.n_steps, 1)
         sel = np.arange(0, w.n_omega, kw)
         sub = {k: v[:ns] for k, v in st.items()}
         samples = flatten(sub, times[:ns])
         log(f"[bench] cpu oracle: {ns} steps x {n} particles x {w.n_dir} dirs x {len(sel)} omega on {cores} threads")
         tc = time.perf_counter()
-        Iref = oracle.spectrum(samples, w.directions(), w.omegas()[sel], w.shape, w.shape_len, w.dt)
+        Iref = oracle.spectrum(samples, w.directions(), omegas[sel], w.shape, w.shape_len, w.dt)
         cpu_s = time.perf_counter() - tc
         cpu_updates = ns * n * w.n_dir * len(sel)
         cpu = {"value": cpu_updates / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -236,6 +248,8 @@ def main() -> int:
         "config": {"workload": w.name, "particles": w.n_particles, "time_steps": w.n_steps,
                    "directions": w.n_dir, "frequencies": w.n_omega, "omega_max": w.omega_max,
                    "shape": w.shape, "shape_len": w.shape_len, "input_dtype": w.in_dtype,
+                   "omega_grid": args.omega_grid if om_list is None else
+                   f"log-spaced list {om_list[0]:.3e}..{om_list[-1]:.3e}",
                    "phase": "f64", "updates_per_step": updates_per_step, "tile": tile},
         "roofline": roofline,
         "cpu_baseline": cpu,

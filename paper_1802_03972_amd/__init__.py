@@ -90,9 +90,9 @@ class Grid:
         _lib.check(L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc)))
         self._h = h
         self.variant = (1 if self._omegas is not None else 0) | (2 if sid >= 5 else 0)
-        if tile == "auto" and self.variant == 0:
+        if tile == "auto":
             from .autotune import lookup
-            t = lookup(self.n_dir, self.n_omega, int(precision))
+            t = lookup(self.n_dir, self.n_omega, int(precision), variant=self.variant)
             if t is not None:
                 self.set_tile(**t)
         elif isinstance(tile, dict):

@@ -22,8 +22,10 @@ LDS_LIMIT = 160 * 1024
 CHUNK = 32
 
 
-def key(n_dir: int, n_omega: int, precision: int) -> str:
-    return f"{int(n_dir)}x{int(n_omega)}:p{int(precision)}"
+def key(n_dir: int, n_omega: int, precision: int, variant: int = 0) -> str:
+    """Table key; variant bit 1 = explicit frequency list, bit 2 = direction-dependent shape."""
+    k = f"{int(n_dir)}x{int(n_omega)}:p{int(precision)}"
+    return k + (f":v{int(variant)}" if variant else "")
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -34,8 +36,8 @@ def load_table(path: str = TABLE) -> dict:
         return {}
 
 
-def lookup(n_dir: int, n_omega: int, precision: int, path: str = TABLE):
-    e = load_table(path).get(key(n_dir, n_omega, precision))
+def lookup(n_dir: int, n_omega: int, precision: int, path: str = TABLE, variant: int = 0):
+    e = load_table(path).get(key(n_dir, n_omega, precision, variant))
     return None if e is None else e["tile"]
 
 
@@ -44,9 +46,9 @@ def lds_bytes(w: int, dpw: int, waves: int) -> int:
     return CHUNK * td * 16 + CHUNK * td * 8 + 11 * CHUNK * 8 + CHUNK * 8 + CHUNK * to * 4
 
 
-def candidates(n_dir: int, n_omega: int):
+def candidates(n_dir: int, n_omega: int, variant: int = 0):
     out = []
-    for w in (16, 32):
+    for w in ((16,) if variant else (16, 32)):     # the variant kernels exist for 16 only
         for dpw in (16, 32, 64):
             for waves in (1, 2, 4, 8):
                 to = waves * (64 // dpw) * w
@@ -86,7 +88,7 @@ def synthetic_particles(n: int, dtype: str, device: int = 0, seed: int = 0) -> d
 
 
 def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_particles: int = 65536,
-         reps: int = 5, device: int = 0, verbose: bool = True) -> dict:
+         reps: int = 5, device: int = 0, verbose: bool = True, variant: int = 0) -> dict:
     import numpy as np
     import torch
 
@@ -98,11 +100,12 @@ def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_par
         tx, ty = th[i % len(th)], th[(i // len(th)) % len(th)] * 0.5
         dirs.append([tx, ty, (1 - tx * tx - ty * ty) ** 0.5])
     parts = synthetic_particles(n_particles, dtype, device)
-    g = Grid(np.array(dirs), 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic", shape_len=1e-7,
-             dt=5e-17, precision=precision, device=device)
+    om = np.geomspace(1e15, 1e19, n_omega) if variant & 1 else None
+    g = Grid(np.array(dirs), 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic3d" if variant & 2 else "cic",
+             shape_len=1e-7, dt=5e-17, precision=precision, device=device, tile=None, omegas=om)
     stream = torch.cuda.current_stream(device)
     results = []
-    for c in candidates(n_dir, n_omega):
+    for c in candidates(n_dir, n_omega, variant):
         g.set_tile(**c)
         g.push_step(0.0, parts, stream)        # warm-up (also instantiates the kernel)
         torch.cuda.synchronize()
@@ -182,6 +185,8 @@ def main():
     ap.add_argument("--omegas", type=int, nargs="+", required=True)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="1: explicit frequency list, 2: cubic-cell shape, 3: both")
     ap.add_argument("--particles", type=int, default=65536)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=TABLE, help="table to update (default: the package's table)")
@@ -202,9 +207,9 @@ def main():
         return
     for nd, no in zip(a.dirs, a.omegas):
         print(f"tuning {nd} directions x {no} frequencies ({a.dtype}, precision {a.precision})", flush=True)
-        r = tune(nd, no, a.dtype, a.precision, a.particles, a.reps)
+        r = tune(nd, no, a.dtype, a.precision, a.particles, a.reps, variant=a.variant)
         r["dtype"] = a.dtype
-        table[key(nd, no, a.precision)] = r
+        table[key(nd, no, a.precision, a.variant)] = r
         print(f"best {r['tile']} at {r['updates_per_s']:.3e} updates/s", flush=True)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)

@@ -28,3 +28,12 @@ def test_table_lookup(tmp_path):
     assert autotune.lookup(128, 256, 0, str(p)) == tile
     assert autotune.lookup(128, 256, 1, str(p)) is None
     assert autotune.lookup(64, 256, 0, str(tmp_path / "missing.json")) is None
+
+
+def test_variant_candidates_and_keys():
+    from paper_1802_03972_amd import autotune
+    for v in (1, 2, 3):
+        cs = autotune.candidates(128, 256, variant=v)
+        assert cs and all(c["w_per_lane"] == 16 for c in cs)
+        assert autotune.key(128, 256, 0, v).endswith(f":v{v}")
+    assert autotune.key(128, 256, 0) == "128x256:p0"
