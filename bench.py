@@ -73,12 +73,13 @@ def calibrate_copy(mib: int) -> int:
 def profiled_traffic(profile: str, tile: dict):
     """HBM bytes per launch of the accumulate kernel from the committed rocprofv3 summary,
     or None if the kernel source or the launch shape changed since those counters were taken."""
-    import hashlib
+    from paper_1802_03972_amd.build import accumulate_source_sha256
+    if not tile:
+        return None
     path = os.path.join(ROOT, "profiles", profile)
-    src = os.path.join(ROOT, "paper_1802_03972_amd", "csrc", "rad_kernels.hip")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = accumulate_source_sha256()
     except OSError:
         return None
     vals = {}
@@ -354,7 +355,10 @@ def bench_batched(args) -> int:
         "speedup_vs_per_bunch": t_pb / t_b,
         "batched_vs_per_bunch_e_inf": agree,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                     "traffic": profiled_traffic("k_accumulate_batch_batched_uneven.md", batcher.get_tile()),
+                     "traffic_source": "profiles/k_accumulate_batch_batched_uneven.md (FETCH_SIZE and WRITE_SIZE "
+                                       "scaled by the copy-kernel calibration, bytes per launch)",
                      "kernel": "k_accumulate_batch", "avg_launch_ms": round(avg_ms, 4),
                      "fold_ms_per_launch": round(prof["fold_ms"] / max(1, prof["launches"]), 4)},
     }

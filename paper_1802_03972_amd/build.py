@@ -13,7 +13,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librad.so")
-SOURCES = ["rad_kernels.hip", "rad_runtime.hip", "rad_server.hip"]
+SOURCES = ["rad_accumulate.hip", "rad_kernels.hip", "rad_runtime.hip", "rad_server.hip"]
+# the files that define the accumulate kernels (profiles taken on them are keyed to their hash)
+ACCUMULATE_FILES = ["rad_internal.h", "rad_device.h", "rad_accumulate.hip"]
 ARCH = os.environ.get("RAD_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -21,6 +23,16 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument",
 ]
+
+
+def accumulate_source_sha256() -> str:
+    """sha256 over the accumulate kernels' source files, in ACCUMULATE_FILES order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ACCUMULATE_FILES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def hipcc() -> str:
