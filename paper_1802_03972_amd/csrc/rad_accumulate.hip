@@ -145,8 +145,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             float zr = 1.f, zi = 0.f;
             if constexpr (!DIRECT) {
                 if constexpr (PREC == 0) {
-                    double rv = om_first * ph;
-                    rv -= floor(rv);
+                    const double rv = frac_rev(om_first * ph);
                     sincos_rev_fast(static_cast<float>(rv), zi, zr);
                 } else {
                     float rv = (float)om_first * (float)ph;
@@ -180,8 +179,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                         // explicit frequency list: each term's phase from the FP64 product,
                         // reduced to [0, 1) revolutions before leaving FP64
                         if constexpr (PREC == 0) {
-                            double rv = om[k] * ph;
-                            rv -= floor(rv);
+                            const double rv = frac_rev(om[k] * ph);
                             sincos_rev_fast(static_cast<float>(rv), zi, zr);
                         } else {
                             float rv = (float)om[k] * (float)ph;

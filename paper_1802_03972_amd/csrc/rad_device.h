@@ -16,6 +16,10 @@ namespace {
 constexpr double kInvC = 1.0 / 299792458.0;          // 1/c [s/m]
 constexpr double kInv2Pi = 0.15915494309189533577;   // 1/(2 pi)
 
+// Fractional part x - floor(x) of an FP64 phase in revolutions (one v_fract_f64; the
+// result lies in [0, 1], and 1 is the same angle as 0).
+__device__ __forceinline__ double frac_rev(double x) { return __builtin_amdgcn_fract(x); }
+
 // sin and cos of 2*pi*r, r in revolutions (the hardware transcendental takes revolutions).
 __device__ __forceinline__ void sincos_rev_fast(float r, float& s, float& c)
 {
@@ -77,8 +81,7 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         wr = 1.f;
         wi = 0.f;
         if constexpr (WANT_W) {
-            double rw = domega * ph;
-            rw -= floor(rw);
+            const double rw = frac_rev(domega * ph);
             sincos_rev_fast(static_cast<float>(rw), wi, wr);
         }
         bad = !(D > 0.0) || !(N >= 0.0) || !isfinite(N) || !isfinite(ph) || !isfinite(A1) ||

@@ -45,15 +45,13 @@ __global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
     const int o0 = ob * W;
     float zr = 1.f, zi = 0.f;
     if constexpr (!DIRECT) {
-        double rv = a.omega[o0] * ph;
-        rv -= floor(rv);
+        const double rv = frac_rev(a.omega[o0] * ph);
         sincos_rev_fast(static_cast<float>(rv), zi, zr);
     }
     double* T = a.T + ((m * a.n_omega + o0) * a.n_dir + d) * 4;
     for (int k = 0; k < W && o0 + k < a.n_omega; ++k, T += (int64_t)a.n_dir * 4) {
         if constexpr (DIRECT) {
-            double rv = a.omega[o0 + k] * ph;
-            rv -= floor(rv);
+            const double rv = frac_rev(a.omega[o0 + k] * ph);
             sincos_rev_fast(static_cast<float>(rv), zi, zr);
         }
         T[0] += (double)(gv.x * zr);
@@ -76,9 +74,10 @@ __global__ void k_tracked_finalize(const double* __restrict__ T, const double* _
                                    int64_t n_particles, int n_dir, int n_omega, double C,
                                    double* __restrict__ I)
 {
+    // consecutive threads take consecutive directions, so the reads of T are contiguous
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)n_dir * n_omega) return;
-    const int d = (int)(i / n_omega), k = (int)(i % n_omega);
+    const int k = (int)(i / n_dir), d = (int)(i % n_dir);
     const double g = g3 ? g3[(int64_t)d * n_omega + k] : gk[k];
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int64_t m = 0; m < n_particles; ++m) {
@@ -87,7 +86,7 @@ __global__ void k_tracked_finalize(const double* __restrict__ T, const double* _
         const double* t = T + ((m * n_omega + k) * n_dir + d) * 4;
         s0 += F * t[0]; s1 += F * t[1]; s2 += F * t[2]; s3 += F * t[3];
     }
-    I[i] = C * (s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3);
+    I[(int64_t)d * n_omega + k] = C * (s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3);
 }
 
 // S[i] += sum over splits of part[s][i], in split order, in FP64.

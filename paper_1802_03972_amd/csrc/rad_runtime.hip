@@ -375,6 +375,67 @@ int read_err_flag(rad_grid* g, hipStream_t st, int* flag)
 
 }  // namespace
 
+namespace {
+
+// Validated host-side tables of a grid description: directions with their normal basis
+// (n, e1, e2), the frequency list, the recurrence step, the Eq. 13 prefactor and the
+// kernel variant.  check_shape = false skips the shape fields (chosen later).
+struct GridTables {
+    std::vector<double> dirs9, om;
+    double domega = 0.0, C = 0.0;
+    int variant = 0;
+};
+
+int prepare_tables(const rad_grid_desc* d, bool check_shape, GridTables& tb)
+{
+    if (d->n_dir < 1 || !d->dirs) return fail(RAD_ERR_INVALID_ARG, "need n_dir >= 1 and dirs");
+    if (d->n_omega < 1) return fail(RAD_ERR_INVALID_ARG, "need n_omega >= 1");
+    if (d->omegas) {
+        for (int k = 0; k < d->n_omega; ++k)
+            if (!(d->omegas[k] >= 0.0) || !std::isfinite(d->omegas[k]))
+                return fail(RAD_ERR_INVALID_ARG, "omegas[%d] must be finite and >= 0", k);
+    } else if (!(d->omega0 >= 0.0) || !std::isfinite(d->omega0) || !(d->domega >= 0.0) || !std::isfinite(d->domega)) {
+        return fail(RAD_ERR_INVALID_ARG, "omega0 and domega must be finite and >= 0");
+    }
+    if (check_shape) {
+        if (d->shape < RAD_SHAPE_POINT || d->shape > RAD_SHAPE_QSC3D)
+            return fail(RAD_ERR_INVALID_ARG, "unknown shape %d", d->shape);
+        if (d->shape != RAD_SHAPE_POINT && !(d->shape_len > 0.0 && std::isfinite(d->shape_len)))
+            return fail(RAD_ERR_INVALID_ARG, "shape_len must be finite and > 0");
+    }
+    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(RAD_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (d->precision != RAD_PHASE_F64 && d->precision != RAD_ALL_F32)
+        return fail(RAD_ERR_INVALID_ARG, "unknown precision mode %d", d->precision);
+    const int64_t points = (int64_t)d->n_dir * d->n_omega;
+    if (points > (int64_t)1 << 28) return fail(RAD_ERR_INVALID_ARG, "grid of %lld points too large", (long long)points);
+    tb.dirs9.resize((size_t)d->n_dir * 9);
+    for (int i = 0; i < d->n_dir; ++i) {
+        const double* n = d->dirs + 3 * i;
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (!std::isfinite(len) || std::fabs(len - 1.0) > 1e-6)
+            return fail(RAD_ERR_INVALID_ARG, "direction %d is not a unit vector (|n| = %.17g)", i, len);
+        double* o = tb.dirs9.data() + 9 * i;
+        o[0] = n[0]; o[1] = n[1]; o[2] = n[2];
+        normal_basis(n, o + 3, o + 6);
+    }
+    tb.om.resize((size_t)d->n_omega);
+    for (int k = 0; k < d->n_omega; ++k) {
+        if (d->omegas) {
+            tb.om[k] = d->omegas[k];
+        } else {
+            volatile double kd = (double)k * d->domega;  // one rounding per operation, no fma
+            tb.om[k] = d->omega0 + kd;
+        }
+    }
+    tb.domega = d->omegas ? 0.0 : d->domega;
+    const double q = kQe * d->dt;
+    tb.C = q * q / (16.0 * kPi * kPi * kPi * kEps0 * kC);
+    tb.variant = (d->omegas ? rad::kVarDirect : 0) | (check_shape && is_shape3(d->shape) ? rad::kVarShape3 : 0);
+    return RAD_OK;
+}
+
+}  // namespace
+
 void rad::set_last_error(const char* msg) { t_last_error = msg ? msg : ""; }
 
 extern "C" {
@@ -396,34 +457,11 @@ int rad_device_cus(int32_t device)
 int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
 {
     if (!out || !d) return fail(RAD_ERR_INVALID_ARG, "out and desc must be non-NULL");
-    if (d->n_dir < 1 || !d->dirs) return fail(RAD_ERR_INVALID_ARG, "need n_dir >= 1 and dirs");
-    if (d->n_omega < 1) return fail(RAD_ERR_INVALID_ARG, "need n_omega >= 1");
-    if (d->omegas) {
-        for (int k = 0; k < d->n_omega; ++k)
-            if (!(d->omegas[k] >= 0.0) || !std::isfinite(d->omegas[k]))
-                return fail(RAD_ERR_INVALID_ARG, "omegas[%d] must be finite and >= 0", k);
-    } else if (!(d->omega0 >= 0.0) || !std::isfinite(d->omega0) || !(d->domega >= 0.0) || !std::isfinite(d->domega)) {
-        return fail(RAD_ERR_INVALID_ARG, "omega0 and domega must be finite and >= 0");
-    }
-    if (d->shape < RAD_SHAPE_POINT || d->shape > RAD_SHAPE_QSC3D)
-        return fail(RAD_ERR_INVALID_ARG, "unknown shape %d", d->shape);
-    if (d->shape != RAD_SHAPE_POINT && !(d->shape_len > 0.0 && std::isfinite(d->shape_len)))
-        return fail(RAD_ERR_INVALID_ARG, "shape_len must be finite and > 0");
-    if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(RAD_ERR_INVALID_ARG, "dt must be finite and > 0");
-    if (d->precision != RAD_PHASE_F64 && d->precision != RAD_ALL_F32)
-        return fail(RAD_ERR_INVALID_ARG, "unknown precision mode %d", d->precision);
+    GridTables tb;
+    int vrc = prepare_tables(d, true, tb);
+    if (vrc) return vrc;
     const int64_t points = (int64_t)d->n_dir * d->n_omega;
-    if (points > (int64_t)1 << 28) return fail(RAD_ERR_INVALID_ARG, "grid of %lld points too large", (long long)points);
-    std::vector<double> dirs9((size_t)d->n_dir * 9);
-    for (int i = 0; i < d->n_dir; ++i) {
-        const double* n = d->dirs + 3 * i;
-        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-        if (!std::isfinite(len) || std::fabs(len - 1.0) > 1e-6)
-            return fail(RAD_ERR_INVALID_ARG, "direction %d is not a unit vector (|n| = %.17g)", i, len);
-        double* o = dirs9.data() + 9 * i;
-        o[0] = n[0]; o[1] = n[1]; o[2] = n[2];
-        normal_basis(n, o + 3, o + 6);
-    }
+    std::vector<double>& dirs9 = tb.dirs9;
     const int cus = rad_device_cus(d->device);
     if (cus < 0) return cus;
 
@@ -438,21 +476,14 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     g->shape_len = d->shape_len;
     g->precision = d->precision;
     g->cus = cus;
-    const double q = kQe * d->dt;
-    g->C = q * q / (16.0 * kPi * kPi * kPi * kEps0 * kC);
-    g->variant = (d->omegas ? rad::kVarDirect : 0) | (is_shape3(d->shape) ? rad::kVarShape3 : 0);
-    if (d->omegas) g->domega = 0.0;
+    g->C = tb.C;
+    g->variant = tb.variant;
+    g->domega = tb.domega;
     g->tile = default_tile(d->n_dir, d->n_omega, g->variant);
 
-    std::vector<double> om((size_t)d->n_omega);
+    std::vector<double>& om = tb.om;
     std::vector<float2> gt((size_t)d->n_omega);
     for (int k = 0; k < d->n_omega; ++k) {
-        if (d->omegas) {
-            om[k] = d->omegas[k];
-        } else {
-            volatile double kd = (double)k * d->domega;  // one rounding per operation, no fma
-            om[k] = d->omega0 + kd;
-        }
         const double gg = is_shape3(d->shape) ? 0.0 : shape_factor(d->shape, d->shape_len, om[k]);
         gt[k] = make_float2((float)gg, (float)(1.0 - gg));
     }
@@ -1235,48 +1266,45 @@ extern "C" int rad_tracked_create(rad_tracked** out, const rad_grid_desc* d, int
     if (!out || !d) return fail(RAD_ERR_INVALID_ARG, "out and desc must be non-NULL");
     if (n_particles < 1) return fail(RAD_ERR_INVALID_ARG, "need n_particles >= 1");
     if (d->precision != RAD_PHASE_F64) return fail(RAD_ERR_INVALID_ARG, "tracked particles use the FP64-phase mode");
-    // reuse the grid validation (directions, frequencies, dt) with a neutral shape
-    rad_grid_desc chk = *d;
-    chk.shape = RAD_SHAPE_POINT;
-    rad_grid* probe = nullptr;
-    int rc = rad_create_grid(&probe, &chk);
+    GridTables tb;
+    int rc = prepare_tables(d, false, tb);
     if (rc) return rc;
+    const int64_t points = (int64_t)d->n_dir * d->n_omega;
+    // 32 B per particle and grid point; refuse sizes whose byte count would not fit
+    if (n_particles > ((int64_t)1 << 50) / (points * 32))
+        return fail(RAD_ERR_INVALID_ARG, "%lld tracked particles x %lld points is too large",
+                    (long long)n_particles, (long long)points);
     rad_tracked* tr = new rad_tracked;
     tr->device = d->device;
     tr->n_particles = n_particles;
     tr->n_dir = d->n_dir;
     tr->n_omega = d->n_omega;
-    tr->domega = probe->domega;
+    tr->domega = tb.domega;
     tr->dt = d->dt;
-    tr->C = probe->C;
-    tr->direct = (probe->variant & rad::kVarDirect) != 0;
+    tr->C = tb.C;
+    tr->direct = (tb.variant & rad::kVarDirect) != 0;
     tr->dirs.assign(d->dirs, d->dirs + 3 * (size_t)d->n_dir);
-    tr->om.resize((size_t)d->n_omega);
+    tr->om = tb.om;
     DeviceGuard dg(d->device);
-    const int64_t points = (int64_t)d->n_dir * d->n_omega;
     const size_t tbytes = (size_t)n_particles * points * 4 * sizeof(double);
-    if (hipMalloc(&tr->d_dirs9, (size_t)d->n_dir * 9 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&tr->d_omega, (size_t)d->n_omega * sizeof(double)) != hipSuccess ||
+    if (hipMalloc(&tr->d_dirs9, tb.dirs9.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tr->d_omega, tb.om.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&tr->d_T, tbytes) != hipSuccess ||
         hipMalloc(&tr->d_w, (size_t)n_particles * sizeof(double)) != hipSuccess ||
         hipMalloc(&tr->d_g, (size_t)points * sizeof(double)) != hipSuccess ||
         hipMalloc(&tr->d_I, (size_t)points * sizeof(double)) != hipSuccess ||
         hipMalloc(&tr->d_err, sizeof(int)) != hipSuccess) {
-        rad_destroy_grid(probe);
         free_tracked(tr);
         return fail(RAD_ERR_OOM, "cannot allocate %zu B of per-particle integrals", tbytes);
     }
     hipError_t e;
-    if ((e = hipMemcpy(tr->d_dirs9, probe->d_dirs9, (size_t)d->n_dir * 9 * sizeof(double), hipMemcpyDeviceToDevice)) != hipSuccess ||
-        (e = hipMemcpy(tr->d_omega, probe->d_omega, (size_t)d->n_omega * sizeof(double), hipMemcpyDeviceToDevice)) != hipSuccess ||
-        (e = hipMemcpy(tr->om.data(), probe->d_omega, (size_t)d->n_omega * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess ||
+    if ((e = hipMemcpy(tr->d_dirs9, tb.dirs9.data(), tb.dirs9.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(tr->d_omega, tb.om.data(), tb.om.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = rad::launch_fill(tr->d_T, (int64_t)(tbytes / sizeof(double)), 0.0, nullptr)) != hipSuccess ||
         (e = rad::launch_fill_int(tr->d_err, 1, 0, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
-        rad_destroy_grid(probe);
         free_tracked(tr);
         return hip_fail(e, "tracked initialisation");
     }
-    rad_destroy_grid(probe);
     *out = tr;
     return RAD_OK;
 }
