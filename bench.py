@@ -44,9 +44,11 @@ def parse():
                     help="batched_uneven: distinct generated steps per bunch, cycled over its 200 steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-pushes", type=int, default=100)
-    ap.add_argument("--omega-grid", choices=("uniform", "log"), default="uniform",
+    ap.add_argument("--omega-grid", choices=("uniform", "log", "blocklog"), default="uniform",
                     help="single_bunch_fp32: 'log' passes the frequencies as an explicit log-spaced list "
-                         "(1e-4 * omega_max .. omega_max), evaluated with a per-term FP64 phase")
+                         "(1e-4 * omega_max .. omega_max), evaluated with a per-term FP64 phase; 'blocklog' "
+                         "spans the same range uniformly inside each block of 16 and log-like across "
+                         "blocks (recurrence with a per-block step)")
     ap.add_argument("--shape", default="", help="single_bunch_fp32: override the macro-particle shape "
                                                 "(e.g. cic3d for the direction-dependent cubic cell)")
     ap.add_argument("--tile", default="", help="override launch shape: w_per_lane,dir_per_wave,waves,wg_per_cu")
@@ -126,7 +128,12 @@ def main() -> int:
     w = SINGLE if args.workload == "single_bunch_fp32" else TINY
     if args.shape:
         w = w.scaled(shape=args.shape)
-    om_list = np.geomspace(1e-4 * w.omega_max, w.omega_max, w.n_omega) if args.omega_grid == "log" else None
+    om_list = None
+    if args.omega_grid == "log":
+        om_list = np.geomspace(1e-4 * w.omega_max, w.omega_max, w.n_omega)
+    elif args.omega_grid == "blocklog":
+        from workloads import block_log_omegas
+        om_list = block_log_omegas(1e-4 * w.omega_max, w.omega_max, w.n_omega)
     omegas = om_list if om_list is not None else w.omegas()
     variant = bool(args.shape) or om_list is not None
     big = args.workload == "single_bunch_fp32"
@@ -250,7 +257,8 @@ def main() -> int:
                    "directions": w.n_dir, "frequencies": w.n_omega, "omega_max": w.omega_max,
                    "shape": w.shape, "shape_len": w.shape_len, "input_dtype": w.in_dtype,
                    "omega_grid": args.omega_grid if om_list is None else
-                   f"log-spaced list {om_list[0]:.3e}..{om_list[-1]:.3e}",
+                   f"{args.omega_grid} list {om_list[0]:.3e}..{om_list[-1]:.3e}",
+                   "kernel_variant": g.variant,
                    "phase": "f64", "updates_per_step": updates_per_step, "tile": tile},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -83,9 +83,12 @@ typedef struct rad_grid_desc {
     int32_t device;      /* HIP device ordinal                                          */
     const double* omegas;/* optional HOST list of n_omega frequencies [rad/s] (finite, >= 0,
                             any spacing, e.g. logarithmic); NULL: the uniform grid above.
-                            With a list, each term's phase is evaluated from FP64 (no
-                            frequency recurrence) and launch shapes use 16 frequencies
-                            per lane                                                     */
+                            The list is classified at creation (rad_grid_variant):
+                            uniform to a few FP64 ulps -> the uniform grid; every aligned
+                            block of 16 entries an arithmetic progression (piecewise-
+                            uniform) -> the frequency recurrence with a per-block step;
+                            otherwise each term's phase is evaluated from FP64.  Lists
+                            that are not uniform use 16 frequencies per lane            */
 } rad_grid_desc;
 
 /* One batch of macro-particles, structure of arrays, all fields the same type. */
@@ -165,6 +168,13 @@ typedef struct rad_tile {
 } rad_tile;
 int rad_get_tile(const rad_grid* g, rad_tile* t);
 int rad_set_tile(rad_grid* g, const rad_tile* t);
+
+/* Kernel variant chosen for a grid at creation, as bits (or a negative code):
+ *   1  explicit frequency list, per-term FP64 phase
+ *   2  direction-dependent (cubic-cell) shape factor
+ *   4  piecewise-uniform frequency list, recurrence with a per-block step
+ * 0 is the uniform frequency grid with a 1-D shape.  Launch-shape tables key on it. */
+int rad_grid_variant(const rad_grid* g);
 
 /* Kernel timing of one grid.  While enabled, every accumulate launch and every fold
  * launch of the grid is bracketed by HIP events recorded on the launch's own stream.

@@ -89,7 +89,9 @@ class Grid:
         h = ctypes.c_void_p()
         _lib.check(L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc)))
         self._h = h
-        self.variant = (1 if self._omegas is not None else 0) | (2 if sid >= 5 else 0)
+        v = L.rad_grid_variant(h)
+        _lib.check(min(v, 0))
+        self.variant = int(v)       # kernel variant bits chosen by the library
         if tile == "auto":
             from .autotune import lookup
             t = lookup(self.n_dir, self.n_omega, int(precision), variant=self.variant)

@@ -91,6 +91,7 @@ SIGNATURES = {
     "rad_get_state": (ctypes.c_int, [_vp, _dp, _vp]),
     "rad_set_state": (ctypes.c_int, [_vp, _dp, _vp]),
     "rad_last_error": (ctypes.c_char_p, []),
+    "rad_grid_variant": (ctypes.c_int, [_vp]),
     "rad_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
     "rad_set_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
     "rad_device_cus": (ctypes.c_int, [ctypes.c_int32]),

@@ -23,7 +23,8 @@ CHUNK = 32
 
 
 def key(n_dir: int, n_omega: int, precision: int, variant: int = 0) -> str:
-    """Table key; variant bit 1 = explicit frequency list, bit 2 = direction-dependent shape."""
+    """Table key; variant bits: 1 explicit frequency list, 2 direction-dependent shape,
+    4 piecewise-uniform frequency list."""
     k = f"{int(n_dir)}x{int(n_omega)}:p{int(precision)}"
     return k + (f":v{int(variant)}" if variant else "")
 
@@ -100,7 +101,14 @@ def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_par
         tx, ty = th[i % len(th)], th[(i // len(th)) % len(th)] * 0.5
         dirs.append([tx, ty, (1 - tx * tx - ty * ty) ** 0.5])
     parts = synthetic_particles(n_particles, dtype, device)
-    om = np.geomspace(1e15, 1e19, n_omega) if variant & 1 else None
+    om = None
+    if variant & 1:
+        om = np.geomspace(1e15, 1e19, n_omega)
+    elif variant & 4:           # uniform inside each 16-block, log-like across blocks
+        nb = -(-n_omega // 16)
+        R = (1e19 / 1e15) ** (1.0 / nb)
+        om = np.concatenate([1e15 * R ** b + np.arange(16) * (1e15 * R ** b * (R - 1) / 16) for b in range(nb)])
+        om = om[:n_omega]
     g = Grid(np.array(dirs), 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic3d" if variant & 2 else "cic",
              shape_len=1e-7, dt=5e-17, precision=precision, device=device, tile=None, omegas=om)
     stream = torch.cuda.current_stream(device)
@@ -186,7 +194,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0,
-                    help="1: explicit frequency list, 2: cubic-cell shape, 3: both")
+                    help="bits: 1 explicit frequency list, 2 cubic-cell shape, 4 piecewise-uniform list")
     ap.add_argument("--particles", type=int, default=65536)
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--out", default=TABLE, help="table to update (default: the package's table)")

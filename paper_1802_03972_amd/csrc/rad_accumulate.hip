@@ -70,9 +70,15 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
 
     constexpr bool DIRECT = (V & kVarDirect) != 0;
     constexpr bool SHAPE3 = (V & kVarShape3) != 0;
+    constexpr bool BSTEP = (V & kVarBlockStep) != 0;
+    static_assert(!(DIRECT && BSTEP), "a frequency list is either direct or block-stepped");
+    static_assert(!BSTEP || W == kBlockW, "block steps are defined per 16 frequencies");
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
     const double om_first = j.omega[o_first < j.n_omega ? o_first : j.n_omega - 1];
+    // piecewise-uniform list: this lane's block spacing (the lane's frequencies are one block)
+    double bstep = 0.0;
+    if constexpr (BSTEP) bstep = j.bstep[(o_first < j.n_omega ? o_first : j.n_omega - 1) / kBlockW];
     // explicit frequencies (direct phase) and direction-dependent shape factors of this lane
     double om[DIRECT ? W : 1];
     float gl[SHAPE3 ? W : 1];
@@ -120,7 +126,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             dg = dg < j.n_dir ? dg : j.n_dir - 1;
             float4 gv;
             double ph;
-            particle_direction_setup<PREC, !DIRECT>(raw, m, j.dirs9 + 9 * dg, j.domega, gv, ph, j.err);
+            particle_direction_setup<PREC, !DIRECT && !BSTEP>(raw, m, j.dirs9 + 9 * dg, j.domega, gv, ph, j.err);
             geo[i] = gv;
             taus[i] = ph;
         }
@@ -153,7 +159,18 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     sincos_rev_fast(rv, zi, zr);
                 }
             }
-            const float A1 = gm.x, A2 = gm.y, wr = gm.z, wi = gm.w;
+            const float A1 = gm.x, A2 = gm.y;
+            float wr = gm.z, wi = gm.w;
+            if constexpr (BSTEP) {
+                // the block's own rotation exp(i bstep tau), from the FP64 phase
+                if constexpr (PREC == 0) {
+                    sincos_rev_fast(static_cast<float>(frac_rev(bstep * ph)), wi, wr);
+                } else {
+                    float rw = (float)bstep * (float)ph;
+                    rw -= floorf(rw);
+                    sincos_rev_fast(rw, wi, wr);
+                }
+            }
             const float4* fq = reinterpret_cast<const float4*>(ff + m * TO + ob * W);
             float Nm = 0.f, NN1 = 0.f;
             if constexpr (SHAPE3) {
@@ -330,6 +347,12 @@ hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStr
     RAD_SHAPE_CASE(16, 64, 3)
     RAD_SHAPE_CASE(16, 32, 3)
     RAD_SHAPE_CASE(16, 16, 3)
+    RAD_SHAPE_CASE(16, 64, 4)
+    RAD_SHAPE_CASE(16, 32, 4)
+    RAD_SHAPE_CASE(16, 16, 4)
+    RAD_SHAPE_CASE(16, 64, 6)
+    RAD_SHAPE_CASE(16, 32, 6)
+    RAD_SHAPE_CASE(16, 16, 6)
 #undef RAD_SHAPE_CASE
     return hipErrorInvalidValue;
 }

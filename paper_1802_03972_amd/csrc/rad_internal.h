@@ -20,7 +20,9 @@ struct Job {
     const double* omega;    // [n_omega]
     const float2* gtab;     // [n_omega]: (g, 1 - g) of a 1-D shape
     const float* g3;        // [n_dir][n_omega]: g of a 3-D (direction-dependent) shape, or null
-    double domega;          // uniform spacing (unused for explicit, non-uniform frequency lists)
+    const double* bstep;    // [ceil(n_omega / 16)]: spacing inside each 16-frequency block of a
+                            // piecewise-uniform frequency list, or null
+    double domega;          // uniform spacing (unused for explicit frequency lists)
     int32_t n_dir, n_omega;
     int32_t tiles_d, tiles_w;
     int* err;               // sticky data-error flag of the grid
@@ -30,6 +32,9 @@ struct Job {
 // the form factor comes from.
 constexpr int kVarDirect = 1;   // explicit frequency list: phase from FP64 per term (no recurrence)
 constexpr int kVarShape3 = 2;   // direction-dependent shape factor g(n, omega)
+constexpr int kVarBlockStep = 4;  // piecewise-uniform list: recurrence with a per-block step
+// Frequencies per block of a piecewise-uniform list (= frequencies per lane of the variants).
+constexpr int kBlockW = 16;
 
 // Arguments of the per-grid accumulate kernel: block b handles tile b % ntiles of split
 // b / ntiles, i.e. chunks [split * chunks_per_split, +chunks_per_split) of the job.
@@ -73,7 +78,7 @@ struct LaunchShape {
     int w_per_lane;    // 16 | 32 (16 only for variant != 0)
     int dir_per_wave;  // 16 | 32 | 64
     int waves;         // 1..8
-    int variant = 0;   // kVarDirect | kVarShape3 bits
+    int variant = 0;   // kVarDirect | kVarShape3 | kVarBlockStep bits
 };
 
 inline int tile_dirs(const LaunchShape& s) { return s.dir_per_wave; }

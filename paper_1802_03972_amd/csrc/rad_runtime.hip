@@ -139,6 +139,7 @@ struct rad_grid {
     int* d_err = nullptr;
     double* d_out = nullptr;
     float* d_g3 = nullptr;     // [n_dir][n_omega] for 3-D shapes
+    double* d_bstep = nullptr; // per-block spacing of a piecewise-uniform frequency list
     int variant = 0;           // rad::kVarDirect | rad::kVarShape3
     // kernel timing (rad_profile_*)
     bool profiling = false;
@@ -266,6 +267,7 @@ void free_grid(rad_grid* g)
     if (g->d_err) (void)hipFree(g->d_err);
     if (g->d_out) (void)hipFree(g->d_out);
     if (g->d_g3) (void)hipFree(g->d_g3);
+    if (g->d_bstep) (void)hipFree(g->d_bstep);
     delete g;
 }
 
@@ -294,6 +296,7 @@ void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0,
     j.omega = g->d_omega;
     j.gtab = g->d_gtab;
     j.g3 = g->d_g3;
+    j.bstep = g->d_bstep;
     j.domega = g->domega;
     j.n_dir = g->n_dir;
     j.n_omega = g->n_omega;
@@ -382,9 +385,46 @@ namespace {
 // kernel variant.  check_shape = false skips the shape fields (chosen later).
 struct GridTables {
     std::vector<double> dirs9, om;
+    std::vector<double> bstep;   // per 16-frequency block spacing (piecewise-uniform lists)
     double domega = 0.0, C = 0.0;
     int variant = 0;
 };
+
+// How an explicit frequency list can be evaluated.  A list whose every aligned block of
+// kBlockW frequencies is an arithmetic progression (to a few FP64 ulps) runs the rotation
+// recurrence with a per-block step; if the steps also agree and the blocks continue one
+// another, the list is one uniform grid.  Otherwise each term takes its own FP64 phase.
+int classify_list(const std::vector<double>& om, std::vector<double>& bstep, double& domega)
+{
+    const int n = (int)om.size(), W = rad::kBlockW;
+    const int nb = (n + W - 1) / W;
+    bstep.assign((size_t)nb, 0.0);
+    auto close = [](double a, double b) {
+        const double tol = 16.0 * 2.220446049250313e-16 * std::max(std::fabs(a), std::fabs(b));
+        return std::fabs(a - b) <= tol;
+    };
+    for (int b = 0; b < nb; ++b) {
+        const int k0 = b * W, k1 = std::min(n, k0 + W);
+        if (k1 - k0 < 2) continue;
+        const double st = (om[k1 - 1] - om[k0]) / (double)(k1 - 1 - k0);
+        for (int k = k0 + 2; k < k1; ++k)
+            if (!close(om[k], om[k0] + (double)(k - k0) * st)) return rad::kVarDirect;
+        bstep[b] = st;
+    }
+    if (n >= 2) {
+        const double st = (om[n - 1] - om[0]) / (double)(n - 1);
+        bool uniform = true;
+        for (int k = 2; k < n && uniform; ++k) uniform = close(om[k], om[0] + (double)k * st);
+        if (uniform) {
+            domega = st;
+            return 0;
+        }
+    } else {
+        domega = 0.0;
+        return 0;
+    }
+    return rad::kVarBlockStep;
+}
 
 int prepare_tables(const rad_grid_desc* d, bool check_shape, GridTables& tb)
 {
@@ -427,10 +467,13 @@ int prepare_tables(const rad_grid_desc* d, bool check_shape, GridTables& tb)
             tb.om[k] = d->omega0 + kd;
         }
     }
-    tb.domega = d->omegas ? 0.0 : d->domega;
+    tb.domega = d->domega;
+    const int list_kind = d->omegas ? classify_list(tb.om, tb.bstep, tb.domega) : 0;
+    if (list_kind != rad::kVarBlockStep) tb.bstep.clear();
+    if (list_kind == rad::kVarDirect) tb.domega = 0.0;
     const double q = kQe * d->dt;
     tb.C = q * q / (16.0 * kPi * kPi * kPi * kEps0 * kC);
-    tb.variant = (d->omegas ? rad::kVarDirect : 0) | (check_shape && is_shape3(d->shape) ? rad::kVarShape3 : 0);
+    tb.variant = list_kind | (check_shape && is_shape3(d->shape) ? rad::kVarShape3 : 0);
     return RAD_OK;
 }
 
@@ -503,7 +546,8 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
         hipMalloc(&g->d_S, sbytes) != hipSuccess ||
         hipMalloc(&g->d_err, sizeof(int)) != hipSuccess ||
         hipMalloc(&g->d_out, (size_t)points * 6 * sizeof(double)) != hipSuccess ||
-        (!g3.empty() && hipMalloc(&g->d_g3, g3.size() * sizeof(float)) != hipSuccess)) {
+        (!g3.empty() && hipMalloc(&g->d_g3, g3.size() * sizeof(float)) != hipSuccess) ||
+        (!tb.bstep.empty() && hipMalloc(&g->d_bstep, tb.bstep.size() * sizeof(double)) != hipSuccess)) {
         free_grid(g);
         return fail(RAD_ERR_OOM, "device allocation failed for a %lld-point grid", (long long)points);
     }
@@ -522,6 +566,8 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
         (e = hipMemcpy(g->d_omega, om.data(), om.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(g->d_gtab, gt.data(), gt.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
         (!g3.empty() && (e = hipMemcpy(g->d_g3, g3.data(), g3.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (!tb.bstep.empty() &&
+         (e = hipMemcpy(g->d_bstep, tb.bstep.data(), tb.bstep.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) ||
         (e = rad::launch_fill(g->d_S, points * 4, 0.0, nullptr)) != hipSuccess ||
         (e = rad::launch_fill_int(g->d_err, 1, 0, nullptr)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
@@ -657,6 +703,12 @@ int rad_set_state(rad_grid* g, const double* state_host, void* stream)
     if (e != hipSuccess) return hip_fail(e, "set_state");
     RAD_HIP(hipStreamSynchronize(st));
     return RAD_OK;
+}
+
+int rad_grid_variant(const rad_grid* g)
+{
+    if (!g) return fail(RAD_ERR_INVALID_ARG, "grid is NULL");
+    return g->variant;
 }
 
 int rad_get_tile(const rad_grid* g, rad_tile* t)
@@ -1282,7 +1334,9 @@ extern "C" int rad_tracked_create(rad_tracked** out, const rad_grid_desc* d, int
     tr->domega = tb.domega;
     tr->dt = d->dt;
     tr->C = tb.C;
-    tr->direct = (tb.variant & rad::kVarDirect) != 0;
+    // any non-uniform list takes the per-term phase here (tracked sets are small)
+    tr->direct = (tb.variant & (rad::kVarDirect | rad::kVarBlockStep)) != 0;
+    if (tr->direct) tr->domega = 0.0;
     tr->dirs.assign(d->dirs, d->dirs + 3 * (size_t)d->n_dir);
     tr->om = tb.om;
     DeviceGuard dg(d->device);

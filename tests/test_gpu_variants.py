@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import SINGLE, TINY, flatten, direction_grid
+from workloads import SINGLE, TINY, flatten, direction_grid, block_log_omegas
 from tests.helpers import e_inf, to_device
 
 pytestmark = pytest.mark.gpu
@@ -104,3 +104,53 @@ def test_variant_grids_require_16_frequencies_per_lane(rad):
     assert g.get_tile()["w_per_lane"] == 16
     with pytest.raises(rad.RadError):
         g.set_tile(w_per_lane=32)
+
+
+def test_frequency_lists_are_classified(rad):
+    """Uniform list -> the uniform path (0); aligned piecewise-uniform -> per-block step (4);
+    anything else -> per-term phase (1); with a cubic-cell shape bit 2 is added."""
+    d = np.array([[0.0, 0.0, 1.0]])
+    w = SINGLE
+    assert rad.Grid(d, 0.0, 0.0, 0, shape="cic", omegas=w.omegas()).variant == 0
+    assert rad.Grid(d, w.omega0, w.domega, w.n_omega, shape="cic").variant == 0
+    assert rad.Grid(d, 0.0, 0.0, 0, shape="cic", omegas=block_log_omegas(1e14, 1e19, 100)).variant == 4
+    assert rad.Grid(d, 0.0, 0.0, 0, shape="cic3d", omegas=block_log_omegas(1e14, 1e19, 100)).variant == 6
+    assert rad.Grid(d, 0.0, 0.0, 0, shape="cic", omegas=np.geomspace(1e14, 1e19, 100)).variant == 1
+    shifted = block_log_omegas(1e14, 1e19, 64)
+    shifted[5] *= 1.0 + 1e-9                     # one entry off its block's progression
+    assert rad.Grid(d, 0.0, 0.0, 0, shape="cic", omegas=shifted).variant == 1
+
+
+@pytest.mark.parametrize("shape,n_omega,dtype", [("cic", 150, "f32"), ("gauss", 64, "f64"), ("tsc3d", 96, "f32")])
+def test_piecewise_uniform_list_matches_oracle(rad, shape, n_omega, dtype):
+    """Block-stepped recurrence on a log-like list (uniform inside each block of 16, ragged
+    last block for 150) against the oracle on the listed frequencies."""
+    w = SINGLE.scaled(n_particles=800, n_steps=3, nx_dir=4, ny_dir=8, shape=shape, seed=21)
+    st = w.steps()
+    om = block_log_omegas(1e13, 2e19, n_omega)
+    dirs = direction_grid(4, 8, 0.3) if shape.endswith("3d") else w.directions()
+    g = rad.Grid(dirs, 0.0, 0.0, 0, shape=shape, shape_len=w.shape_len, dt=w.dt, omegas=om)
+    assert g.variant & 4
+    g.push_steps(w.t0, w.n_steps, to_device(st, dtype))
+    I = g.spectrum()
+    Iref = oracle.spectrum(flatten(st, w.times()), dirs, om, shape, w.shape_len, w.dt)
+    err = e_inf(I, Iref)
+    col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
+    print(f"block-stepped list ({shape}, {n_omega}, {dtype}): e_inf {err:.3e}, per-frequency {col.max():.3e}")
+    assert err <= TOL and col.max() <= TOL
+
+
+def test_piecewise_uniform_list_batched(rad):
+    om = block_log_omegas(1e14, 1e19, 80)
+    ws = [SINGLE.scaled(n_particles=n, n_steps=2, nx_dir=4, ny_dir=4, seed=50 + k) for k, n in enumerate((500, 2300))]
+    sts = [w.steps() for w in ws]
+    grids = [rad.Grid(w.directions(), 0.0, 0.0, 0, shape=w.shape, shape_len=w.shape_len, dt=w.dt, omegas=om)
+             for w in ws]
+    devs = [to_device(st, "f32") for st in sts]
+    rad.Batcher().push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
+    for g, w, st, d in zip(grids, ws, sts, devs):
+        Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
+        assert e_inf(g.spectrum(), Iref) <= TOL
+        single = rad.Grid(w.directions(), 0.0, 0.0, 0, shape=w.shape, shape_len=w.shape_len, dt=w.dt, omegas=om)
+        single.push_steps(w.t0, w.n_steps, d)
+        assert e_inf(g.spectrum(), single.spectrum()) <= 1e-6

@@ -35,6 +35,21 @@ def omega_grid(omega0: float, domega: float, n: int) -> np.ndarray:
     return omega0 + k * domega
 
 
+def block_log_omegas(lo: float, hi: float, n: int, block: int = 16) -> np.ndarray:
+    """Log-like frequency list that is uniform inside each aligned block of `block`
+    entries: block b starts at s_b = lo * R^b and steps by (s_{b+1} - s_b) / block, so the
+    blocks tile [lo, ~hi] with spacings growing geometrically (R = (hi/lo)^(1/blocks))."""
+    nb = -(-n // block)
+    R = (hi / lo) ** (1.0 / nb)
+    out = np.empty(n, np.float64)
+    for b in range(nb):
+        s0 = lo * R ** b
+        st = (lo * R ** (b + 1) - s0) / block
+        k = np.arange(min(block, n - b * block), dtype=np.float64)
+        out[b * block:b * block + k.size] = s0 + k * st
+    return out
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
