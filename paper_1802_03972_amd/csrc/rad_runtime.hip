@@ -1047,6 +1047,7 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
     const int TD = rad::tile_dirs(ls), TO = rad::tile_omegas(ls);
     const int R_target = std::max(1, b->cus * btile.wg_per_cu);
     const int64_t per_launch = (int64_t)R_target * (kMaxPerWorkgroup / rad::kChunk);
+    hipEvent_t last_done = nullptr;
     for (int64_t L0 = 0; L0 < I; L0 += per_launch) {
         const int64_t L1 = std::min(I, L0 + per_launch);
         const int R = (int)std::min<int64_t>(R_target, L1 - L0);
@@ -1199,6 +1200,22 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         }
         RAD_HIP(hipEventRecord(sl.done, st));
         sl.used = true;
+        last_done = sl.done;
+    }
+    // Later single-grid folds (on each grid's fold stream, whatever stream pushes them) and
+    // read-outs must come after this batch's fold: chain each grid's fold stream behind it.
+    if (last_done) {
+        std::vector<rad_grid*> seen;
+        for (const auto& in : info) {
+            rad_grid* g = in.grid;
+            if (std::find(seen.begin(), seen.end(), g) != seen.end()) continue;
+            seen.push_back(g);
+            RAD_HIP(hipStreamWaitEvent(g->fold_stream, last_done, 0));
+            const int k = g->last_fold >= 0 ? g->last_fold : 0;
+            RAD_HIP(hipEventRecord(g->ev_fold_done[k], g->fold_stream));
+            g->fold_recorded[k] = true;
+            g->last_fold = k;
+        }
     }
     return RAD_OK;
 }

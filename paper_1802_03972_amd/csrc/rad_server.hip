@@ -368,8 +368,13 @@ int rad_server_wait(rad_server* s, uint64_t ticket, rad_chunk_stats* st)
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->chunks.find(ticket);
     if (it == s->chunks.end()) return srv_fail(RAD_ERR_INVALID_ARG, "unknown ticket");
-    s->cv_client.wait(lk, [&] { return s->chunks[ticket].done; });
+    // a ticket collected meanwhile by another waiter counts as unknown
+    s->cv_client.wait(lk, [&] {
+        auto f = s->chunks.find(ticket);
+        return f == s->chunks.end() || f->second.done;
+    });
     it = s->chunks.find(ticket);
+    if (it == s->chunks.end()) return srv_fail(RAD_ERR_INVALID_ARG, "ticket collected by another caller");
     if (st) *st = it->second.st;
     const int status = it->second.st.status;
     s->chunks.erase(it);

@@ -162,3 +162,26 @@ def test_graph_replays_match_direct_launches(rad):
         del junk
     st = gb.graph_stats()
     assert st["failures"] == 0 and st["launches"] == 4 and st["graphs"] >= 1
+
+
+def test_batch_then_single_pushes_on_other_streams(rad):
+    """A batched push on one stream followed, without any host synchronisation, by single
+    pushes of the same grids on another stream and a read-out on a third: every update of
+    the accumulator is ordered, so the result equals the same work done in order."""
+    import torch
+    bs = bunches([3000, 700], steps=2)
+    grids = [grid_for(rad, w) for w, _ in bs]
+    ref = [grid_for(rad, w) for w, _ in bs]
+    devs = [to_device(st, "f32") for _, st in bs]
+    sa, sb, sc = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b = rad.Batcher(max_items=4)
+    b.push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(grids, bs, devs)], sa)
+    for g, (w, _), d in zip(grids, bs, devs):
+        g.push_steps(w.t0 + 5 * w.dt, w.n_steps, d, sb)
+    I = [g.spectrum(sc) for g in grids]
+    for r, (w, _), d in zip(ref, bs, devs):
+        r.push_steps(w.t0, w.n_steps, d)
+        r.push_steps(w.t0 + 5 * w.dt, w.n_steps, d)
+    for a, r in zip(I, ref):
+        assert e_inf(a, r.spectrum()) <= 1e-6
