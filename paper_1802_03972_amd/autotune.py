@@ -2,7 +2,7 @@
 
 For a grid shape (directions x frequencies, particle dtype, arithmetic mode) it times every
 valid launch shape -- frequencies per lane (16, 32), directions per wave (16, 32, 64), waves
-per workgroup (1..8) and workgroups per compute unit in a launch (1, 2, 4) -- on synthetic
+per workgroup (1..8) and workgroups per compute unit in a launch (1..8) -- on synthetic
 particles held
 on the device, measuring whole pushes (accumulate + fold) with device events, and records
 the fastest in a JSON table next to this file.  `Grid(..., tile="auto")` applies the table
@@ -60,7 +60,7 @@ def candidates(n_dir: int, n_omega: int, variant: int = 0):
                 lds = lds_bytes(w, dpw, waves)
                 if lds > LDS_LIMIT:
                     continue
-                for wg in (1, 2, 4):                    # workgroups per CU in one launch
+                for wg in (1, 2, 3, 4, 5, 6, 8):       # workgroups per CU in one launch
                     out.append({"w_per_lane": w, "dir_per_wave": dpw, "waves": waves, "wg_per_cu": wg})
     return out
 
@@ -112,27 +112,47 @@ def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_par
     g = Grid(np.array(dirs), 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic3d" if variant & 2 else "cic",
              shape_len=1e-7, dt=5e-17, precision=precision, device=device, tile=None, omegas=om)
     stream = torch.cuda.current_stream(device)
-    results = []
-    for c in candidates(n_dir, n_omega, variant):
+
+    def measure(c, n_reps):
         g.set_tile(**c)
         g.push_step(0.0, parts, stream)        # warm-up (also instantiates the kernel)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for r in range(reps):
+        for r in range(n_reps):
             g.push_step(r * 5e-17, parts, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / n_reps
+
+    results = []
+    for c in candidates(n_dir, n_omega, variant):
+        ms = measure(c, reps)
         ups = n_particles * n_dir * n_omega / (ms * 1e-3)
         results.append((ms, c, ups))
         if verbose:
             print(f"  {c}: {ms:.4f} ms/push, {ups:.3e} updates/s", flush=True)
+    results = confirm(results, lambda c: measure(c, 4 * reps),
+                      lambda ms: n_particles * n_dir * n_omega / (ms * 1e-3), verbose)
     g.close()
-    results.sort(key=lambda r: r[0])
     ms, best, ups = results[0]
     return {"tile": best, "ms_per_push": ms, "updates_per_s": ups, "n_particles": n_particles,
             "candidates": len(results), "measured_at": time.strftime("%Y-%m-%d")}
+
+
+def confirm(results, remeasure, rate, verbose: bool, top: int = 4):
+    """Second, longer pass over the fastest candidates of the sweep (single timings of a
+    sub-millisecond push vary by a few per cent): re-time the best `top` and rank them by
+    the longer measurement."""
+    results = sorted(results, key=lambda r: r[0])
+    again = []
+    for ms0, c, _ in results[:top]:
+        ms = remeasure(c)
+        again.append((ms, c, rate(ms)))
+        if verbose:
+            print(f"  confirm {c}: {ms:.4f} ms (sweep {ms0:.4f})", flush=True)
+    again.sort(key=lambda r: r[0])
+    return again + results[top:]
 
 
 def batch_key(n_dir: int, n_omega: int, precision: int) -> str:
@@ -163,25 +183,29 @@ def tune_batch(n_dir: int, n_omega: int, counts, dtype: str = "f32", precision: 
     stream = torch.cuda.current_stream(device)
     total = float(sum(counts)) * n_dir * n_omega
     results = []
-    for c in candidates(n_dir, n_omega):
+    items = [(g, 0.0, 1, p) for g, p in zip(grids, parts)]
+
+    def measure(c, n_reps):
         b.set_tile(**c)
-        items = [(g, 0.0, 1, p) for g, p in zip(grids, parts)]
         b.push(items, stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(reps):
+        for _ in range(n_reps):
             b.push(items, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / n_reps
+
+    for c in candidates(n_dir, n_omega):
+        ms = measure(c, reps)
         results.append((ms, c, total / (ms * 1e-3)))
         if verbose:
             print(f"  batch {c}: {ms:.4f} ms/push, {total / (ms * 1e-3):.3e} updates/s", flush=True)
+    results = confirm(results, lambda c: measure(c, 3 * reps), lambda ms: total / (ms * 1e-3), verbose)
     b.close()
     for g in grids:
         g.close()
-    results.sort(key=lambda r: r[0])
     ms, best, ups = results[0]
     return {"tile": best, "ms_per_push": ms, "updates_per_s": ups, "counts": [int(n) for n in counts],
             "candidates": len(results), "measured_at": time.strftime("%Y-%m-%d")}

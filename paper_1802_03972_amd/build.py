@@ -43,6 +43,7 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, extra_flags=()) -> str:
+    """extra_flags: more hipcc flags, e.g. -DRAD_CHUNK=16 or -DRAD_W16_WAVES=4."""
     build_dir = os.path.join(PKG, "_build")
     os.makedirs(build_dir, exist_ok=True)
     objs, cmds = [], []
@@ -69,4 +70,4 @@ def build(verbose: bool = False, extra_flags=()) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, extra_flags=[a for a in sys.argv[1:] if a.startswith("-D")]))

@@ -233,8 +233,27 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     }
 }
 
+// Waves per SIMD the 16-frequency recurrence kernels (uniform grid, per-block step) are
+// compiled for: 4 caps them at 128 VGPRs, so four waves share a SIMD (the issue rate of
+// this VALU-bound loop grows with resident waves; the few spills this costs sit in the
+// per-chunk set-up, not in the hot loop).  The other kernels keep the default for
+// 512-thread workgroups.
+#ifndef RAD_W16_WAVES
+#define RAD_W16_WAVES 4
+#endif
+#ifndef RAD_W16V_WAVES
+#define RAD_W16V_WAVES 2
+#endif
+#ifndef RAD_W32_WAVES
+#define RAD_W32_WAVES 2
+#endif
+constexpr int min_waves(int W, int V)
+{
+    return W == 32 ? RAD_W32_WAVES : ((V == 0 || V == kVarBlockStep) ? RAD_W16_WAVES : RAD_W16V_WAVES);
+}
+
 template <typename InT, int PREC, int W, int DPW, int V>
-__global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
+__global__ void __launch_bounds__(512, min_waves(W, V)) k_accumulate(AccArgs a)
 {
     extern __shared__ float4 smem4[];
     constexpr int TD = DPW;
@@ -259,7 +278,7 @@ __global__ void __launch_bounds__(512) k_accumulate(AccArgs a)
 // each a chunk range of one (item, tile); segment s writes its partial tile [TO][TD] at
 // seg_part + s * TO * TD (float4 units).
 template <typename InT, int PREC, int W, int DPW, int V>
-__global__ void __launch_bounds__(512) k_accumulate_batch(const Job* __restrict__ items,
+__global__ void __launch_bounds__(512, min_waves(W, V)) k_accumulate_batch(const Job* __restrict__ items,
                                                           const int32_t* __restrict__ wg_seg_begin,
                                                           const BatchSeg* __restrict__ segs,
                                                           float* seg_part)

@@ -7,7 +7,10 @@
 namespace rad {
 
 // Particles staged per workgroup chunk (one LDS round).
-constexpr int kChunk = 32;
+#ifndef RAD_CHUNK
+#define RAD_CHUNK 32
+#endif
+constexpr int kChunk = RAD_CHUNK;
 
 // One accumulation source: a particle range of one grid (one push, or one batch item).
 struct Job {

@@ -11,7 +11,7 @@ def test_candidates_are_valid():
         assert cs
         for c in cs:
             assert c["w_per_lane"] in (16, 32) and c["dir_per_wave"] in (16, 32, 64)
-            assert 1 <= c["waves"] <= 8 and c["wg_per_cu"] in (1, 2, 4)
+            assert 1 <= c["waves"] <= 8 and 1 <= c["wg_per_cu"] <= 8
             assert autotune.lds_bytes(c["w_per_lane"], c["dir_per_wave"], c["waves"]) <= autotune.LDS_LIMIT
 
 
