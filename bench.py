@@ -399,6 +399,8 @@ def bench_serving(args) -> int:
                       shape_len=w.shape_len, dt=w.dt) for w in ws]
     per_chunk_updates = np.array([w.n_particles * w.n_dir * w.n_omega for w in ws], dtype=np.float64)
 
+    server_tile = []
+
     def run(rate, n_chunks, seed):
         arrivals, which = poisson_trace(rate, n_chunks, len(ws), seed=seed)
         srv = rad.Server(hbm_budget=4 << 30, max_batch=64, max_inflight=2, max_admitted=256, poll_us=20)
@@ -428,6 +430,7 @@ def bench_serving(args) -> int:
             lat.append(s["t_complete"] - t_arr)
             done.append(s["t_complete"])
             bsz.append(s["batch_size"])
+        server_tile.append(srv.get_tile())
         srv.close()
         total = float(sum(per_chunk_updates[b] for _, b, _ in tickets))
         span = max(done) - (t0 + arrivals[0])
@@ -455,7 +458,7 @@ def bench_serving(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serving", "bunches": len(ws), "counts": list(sv.counts),
                    "directions": ws[0].n_dir, "frequencies": ws[0].n_omega, "rate_chunks_per_s": args.rate,
-                   "chunks": args.chunks, "distinct_generated_steps": kd, "tile": grids[0].get_tile()},
+                   "chunks": args.chunks, "distinct_generated_steps": kd, "batched_tile": server_tile[0]},
         "latency_ms": {"p50": full["p50_ms"], "p99": full["p99_ms"], "unit": "ms",
                        "what": "chunk arrival to completion"},
         "serving": full, "load_scaled": scaled,

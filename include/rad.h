@@ -302,6 +302,12 @@ int rad_server_drain(rad_server* s);
 
 int rad_server_counters_read(rad_server* s, rad_server_counters* out);
 
+/* Launch shape of the server's batched launches (as rad_batcher_set_tile; NULL restores
+ * the library default) and the shape in use (RAD_ERR_INVALID_ARG while the default
+ * applies).  Takes effect from the next batch. */
+int rad_server_set_tile(rad_server* s, const rad_tile* t);
+int rad_server_get_tile(rad_server* s, rad_tile* t);
+
 /* Drain, stop the scheduler thread and free the server (not its grids). */
 int rad_server_destroy(rad_server* s);
 

@@ -288,13 +288,32 @@ class Server:
 
     def __init__(self, device: int = 0, hbm_budget: int = 1 << 30, max_batch: int = 64,
                  max_inflight: int = 2, max_admitted: int = 256, max_pending: int = 1 << 20,
-                 poll_us: int = 20, use_graph: bool = True):
+                 poll_us: int = 20, use_graph: bool = True, tile="auto"):
+        """tile: "auto" applies the autotuner's batched-kernel entry for the first submitted
+        grid's shape (if any), None keeps the library default, or a dict of the four fields."""
         cfg = _lib.ServerConfig(int(device), int(hbm_budget), int(max_batch), int(max_inflight),
                                 int(max_admitted), int(max_pending), int(poll_us), 1 if use_graph else 0)
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().rad_server_create(ctypes.byref(h), ctypes.byref(cfg)))
         self._h = h
         self._keep = {}
+        self._auto = tile == "auto"
+        if isinstance(tile, dict):
+            self.set_tile(**tile)
+
+    def set_tile(self, **kw) -> None:
+        """Launch shape of the batched launches (all four fields), or none for the default."""
+        if not kw:
+            _lib.check(_lib.lib().rad_server_set_tile(self._h, None))
+            return
+        t = _lib.Tile(*[int(kw[k]) for k, _ in _lib.Tile._fields_])
+        _lib.check(_lib.lib().rad_server_set_tile(self._h, ctypes.byref(t)))
+
+    def get_tile(self):
+        t = _lib.Tile()
+        if _lib.lib().rad_server_get_tile(self._h, ctypes.byref(t)) != 0:
+            return None
+        return {k: getattr(t, k) for k, _ in _lib.Tile._fields_}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -309,6 +328,12 @@ class Server:
             pass
 
     def submit(self, grid: "Grid", t: float, host_fields: dict) -> int:
+        if self._auto:
+            from .autotune import lookup_batch
+            tt = lookup_batch(grid.n_dir, grid.n_omega, grid.precision) if grid.variant == 0 else None
+            if tt is not None:
+                self.set_tile(**tt)
+            self._auto = False
         arrs = []
         for k in FIELDS:
             a = host_fields[k]

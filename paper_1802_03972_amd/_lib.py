@@ -114,6 +114,8 @@ SIGNATURES = {
     "rad_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ChunkStats)]),
     "rad_server_drain": (ctypes.c_int, [_vp]),
     "rad_server_counters_read": (ctypes.c_int, [_vp, ctypes.POINTER(ServerCounters)]),
+    "rad_server_set_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
+    "rad_server_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
     "rad_server_destroy": (ctypes.c_int, [_vp]),
     "rad_tracked_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GridDesc), ctypes.c_int64]),
     "rad_tracked_destroy": (ctypes.c_int, [_vp]),

@@ -174,19 +174,20 @@ int max_splits(const rad_grid* g)
 
 rad_tile default_tile(int n_dir, int n_omega, int variant = 0)
 {
+    (void)variant;
     rad_tile t{};
-    // Measured on the single-bunch grid (128 x 256): 64 directions per wave and 8 waves
-    // (one 84 KB workgroup per CU) beats 32 x 4 waves (two per CU) by ~2%.
-    t.dir_per_wave = n_dir <= 16 ? 16 : (n_dir < 48 ? 32 : 64);
-    const int subs = 64 / t.dir_per_wave;
-    t.w_per_lane = (n_omega >= 32 * subs && variant == 0) ? 32 : 16;
-    const int per_wave = subs * t.w_per_lane;
+    // 16 frequencies per lane (the four-waves-per-SIMD kernels); 32 directions per wave
+    // where the grid has them and the frequencies are few, else 16.  Measured winners on
+    // MI355X: 128 x 256 and 64 x 256 -> 32 x 8 waves, 128 x 512 and 64 x 1024 -> 16 x 8.
+    t.w_per_lane = 16;
+    t.dir_per_wave = (n_dir >= 32 && n_omega <= 256) ? 32 : 16;
+    const int per_wave = (64 / t.dir_per_wave) * t.w_per_lane;
     t.waves = std::min(8, std::max(1, (n_omega + per_wave - 1) / per_wave));
-    // Two waves per SIMD (8 per CU) at ~160-256 VGPRs; LDS also bounds the count.
+    // 16 waves per CU fit (128 VGPRs); LDS also bounds the count.
     const size_t lds = rad::acc_lds_bytes(shape_of(t));
-    int by_waves = std::max(1, 8 / t.waves);
-    int by_lds = std::max(1, (int)((160 * 1024) / lds));
-    t.wg_per_cu = std::min(by_waves, by_lds);
+    const int by_waves = std::max(1, 16 / t.waves);
+    const int by_lds = std::max(1, (int)((160 * 1024) / lds));
+    t.wg_per_cu = std::max(2, std::min(by_waves, by_lds));
     return t;
 }
 

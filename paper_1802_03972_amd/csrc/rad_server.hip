@@ -404,6 +404,20 @@ int rad_server_counters_read(rad_server* s, rad_server_counters* out)
     return RAD_OK;
 }
 
+int rad_server_set_tile(rad_server* s, const rad_tile* t)
+{
+    if (!s) return srv_fail(RAD_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);   // the scheduler pushes batches under this lock
+    return rad_batcher_set_tile(s->batcher, t);
+}
+
+int rad_server_get_tile(rad_server* s, rad_tile* t)
+{
+    if (!s || !t) return srv_fail(RAD_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return rad_batcher_get_tile(s->batcher, t);
+}
+
 int rad_server_destroy(rad_server* s)
 {
     if (!s) return RAD_OK;
