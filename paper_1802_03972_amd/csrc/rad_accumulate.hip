@@ -171,6 +171,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     sincos_rev_fast(rw, wi, wr);
                 }
             }
+            // -Im(w) as its own register: the empty asm hides its origin, so the compiler
+            // cannot fold the sign back into a source modifier (a VOP3 encoding)
+            float nwi = -wi;
+            asm volatile("" : "+v"(nwi));
             const float4* fq = reinterpret_cast<const float4*>(ff + m * TO + ob * W);
             float Nm = 0.f, NN1 = 0.f;
             if constexpr (SHAPE3) {
@@ -211,7 +215,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     s2r[k] = fmaf(A2, ur, s2r[k]);
                     s2i[k] = fmaf(A2, ui, s2i[k]);
                     if constexpr (!DIRECT) {
-                        const float nr = fmaf(zr, wr, -(zi * wi));
+                        // z <- z w with -Im(w) held negated, so that every operation is a
+                        // plain product or multiply-add (VOP2 encodings, no modifiers)
+                        const float nr = fmaf(zr, wr, zi * nwi);
                         const float ni = fmaf(zr, wi, zi * wr);
                         zr = nr;
                         zi = ni;
