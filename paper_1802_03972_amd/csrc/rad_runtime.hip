@@ -912,23 +912,27 @@ void build_plan(const std::vector<ItemInfo>& items, int64_t L0, int64_t L1, int 
         }
     }
     pl.wg_seg_begin.push_back((int32_t)pl.segs.size());
-    // fold jobs keyed by (grid, tile), segments listed in segment order
+    // fold jobs keyed by (grid, tile), segments listed in segment order.  The tile index is
+    // in the batch's launch shape (the items' jobs), not the grid's own single-push shape.
     std::map<std::pair<const rad_grid*, int>, std::vector<int32_t>> groups;
     std::vector<std::pair<const rad_grid*, int>> order;
+    std::vector<int> order_tiles_d;
     for (size_t sidx = 0; sidx < pl.segs.size(); ++sidx) {
         const auto& sg = pl.segs[sidx];
         auto key = std::make_pair((const rad_grid*)items[sg.item].grid, (int)sg.tile);
         auto f = groups.find(key);
         if (f == groups.end()) {
             order.push_back(key);
+            order_tiles_d.push_back(items[sg.item].job.tiles_d);
             groups[key].push_back((int32_t)sidx);
         } else {
             f->second.push_back((int32_t)sidx);
         }
     }
-    for (const auto& key : order) {
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const auto& key = order[oi];
         const rad_grid* g = key.first;
-        const int tdn = tiles_d(g);
+        const int tdn = order_tiles_d[oi];
         rad::FoldJob fj{};
         fj.S = g->d_S;
         fj.n_dir = g->n_dir;

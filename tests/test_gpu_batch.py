@@ -87,17 +87,28 @@ def test_several_items_on_one_grid(rad):
     assert e_inf(g_split.spectrum(), g_all.spectrum()) <= 1e-6
 
 
-def test_batch_mixes_grid_shapes_and_tiles(rad):
-    """Grids of different shapes and single-push tiles share one batched launch."""
+@pytest.mark.parametrize("grid_tiles,batch_tile", [
+    # batch tiles coarser than the grids' own in directions
+    ([dict(w_per_lane=16, dir_per_wave=16, waves=2, wg_per_cu=1), None],
+     dict(w_per_lane=32, dir_per_wave=32, waves=4, wg_per_cu=2)),
+    # batch tiles finer than the grids' own: several direction and frequency tiles per grid
+    ([dict(w_per_lane=16, dir_per_wave=64, waves=8, wg_per_cu=1), dict(w_per_lane=32, dir_per_wave=64, waves=2, wg_per_cu=1)],
+     dict(w_per_lane=16, dir_per_wave=16, waves=1, wg_per_cu=3)),
+])
+def test_batch_mixes_grid_shapes_and_tiles(rad, grid_tiles, batch_tile):
+    """Grids of different shapes and single-push tiles share one batched launch; the fold
+    places every partial tile by the batch's own tiling, whatever the grids' tiles are."""
     w1 = SINGLE.scaled(n_particles=900, n_steps=2, nx_dir=4, ny_dir=8, n_omega=100, seed=41)
     w2 = SINGLE.scaled(n_particles=1500, n_steps=2, nx_dir=8, ny_dir=8, n_omega=256, seed=42)
     ws = [w1, w2]
     sts = [w.steps() for w in ws]
     grids = [grid_for(rad, w) for w in ws]
-    grids[0].set_tile(w_per_lane=16, dir_per_wave=16, waves=2, wg_per_cu=1)
+    for g, t in zip(grids, grid_tiles):
+        if t is not None:
+            g.set_tile(**t)
     devs = [to_device(st, w.in_dtype) for w, st in zip(ws, sts)]
     b = rad.Batcher()
-    b.set_tile(w_per_lane=32, dir_per_wave=32, waves=4, wg_per_cu=2)
+    b.set_tile(**batch_tile)
     b.push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
     for g, w, st, d in zip(grids, ws, sts, devs):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)

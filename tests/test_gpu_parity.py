@@ -99,12 +99,13 @@ def test_every_tile_shape_agrees(rad):
     for wpl in (16, 32):
         for dpw in (16, 32, 64):
             for waves in (1, 2, 4, 8):
-                g = make_grid(rad, w)
-                g.set_tile(w_per_lane=wpl, dir_per_wave=dpw, waves=waves, wg_per_cu=1)
-                I = run_gpu(rad, w, st, grid=g).spectrum()
-                err = e_inf(I, Iref)
-                assert err <= TOL, (wpl, dpw, waves, err)
-                g.close()
+                for wg in ((1, 6) if wpl == 16 else (1,)):   # splits per tile also vary
+                    g = make_grid(rad, w)
+                    g.set_tile(w_per_lane=wpl, dir_per_wave=dpw, waves=waves, wg_per_cu=wg)
+                    I = run_gpu(rad, w, st, grid=g).spectrum()
+                    err = e_inf(I, Iref)
+                    assert err <= TOL, (wpl, dpw, waves, wg, err)
+                    g.close()
 
 
 def test_push_steps_matches_per_step_pushes(rad):

@@ -99,3 +99,24 @@ def test_oversized_chunk_rejected(rad):
         srv.submit(g, 0.0, host_chunk(st, 0))
     assert ei.value.code == rad.RAD_ERR_INVALID_ARG
     srv.close()
+
+
+def test_server_launch_shape(rad):
+    """An explicit launch shape for the served batches: reported back, same results."""
+    bs = make_bunches([900, 2100], steps=2)
+    grids = [grid_for(rad, w) for w, _ in bs]
+    tile = {"w_per_lane": 16, "dir_per_wave": 16, "waves": 2, "wg_per_cu": 3}
+    srv = rad.Server(hbm_budget=64 << 20, max_batch=8, tile=tile)
+    assert srv.get_tile() == tile
+    with pytest.raises(rad.RadError):
+        srv.set_tile(w_per_lane=24, dir_per_wave=16, waves=2, wg_per_cu=1)
+    tickets = [srv.submit(g, float(w.times()[j]), host_chunk(st, j))
+               for g, (w, st) in zip(grids, bs) for j in range(w.n_steps)]
+    srv.drain()
+    for tk in tickets:
+        assert srv.wait(tk)["status"] == 0
+    srv.close()
+    for g, (w, st) in zip(grids, bs):
+        direct = grid_for(rad, w)
+        direct.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
+        assert e_inf(g.spectrum(), direct.spectrum()) <= 1e-6
