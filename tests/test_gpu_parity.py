@@ -258,3 +258,56 @@ def test_single_bunch_full_size_sampled(rad):
     err = e_inf(I[:, sel], Iref)
     print(f"single bunch full size (1 step), sampled: e_inf = {err:.3e}")
     assert err <= TOL
+
+
+def test_push_split_over_several_launches(rad):
+    """A single push larger than one launch holds (4 splits x 32768 particles on this
+    tiling) is cut into three launches; same for a batched push over many tiles."""
+    w = SINGLE.scaled(n_particles=300000, n_steps=1, nx_dir=8, ny_dir=16, n_omega=512, seed=31)
+    st = w.steps()
+    dev = to_device(st, "f32")
+    tile = dict(w_per_lane=16, dir_per_wave=16, waves=1, wg_per_cu=1)
+    g = make_grid(rad, w, tile=tile)
+    g.profile(True)
+    g.push_step(float(w.times()[0]), dev)
+    prof = g.profile_read()
+    assert prof["launches"] == 3
+    gb = make_grid(rad, w)
+    b = rad.Batcher(tile=tile)
+    b.push([(gb, float(w.times()[0]), 1, dev)])
+    ds = np.arange(0, w.n_dir, 8)
+    ks = np.r_[np.arange(0, w.n_omega, 64), w.n_omega - 1]
+    Iref = oracle_I(w, st, dirs=w.directions()[ds], omegas=w.omegas()[ks])
+    for grid in (g, gb):
+        err = e_inf(grid.spectrum()[np.ix_(ds, ks)], Iref)
+        print(f"multi-launch push: e_inf {err:.3e}")
+        assert err <= TOL
+
+
+@pytest.mark.parametrize("n_dir,n_omega", [(1, 1), (1, 17), (3, 1)])
+def test_degenerate_grids(rad, n_dir, n_omega):
+    """One direction and/or one frequency (a single 3e18 rad/s line)."""
+    w = TINY.scaled(n_particles=200, n_steps=3, seed=32)
+    st = w.steps()
+    dirs = w.directions()[:n_dir]
+    om0, dom = 3e18, (2e17 if n_omega > 1 else 0.0)
+    g = rad.Grid(dirs, om0, dom, n_omega, shape=w.shape, shape_len=w.shape_len, dt=w.dt)
+    run_gpu(rad, w, st, grid=g)
+    om = om0 + np.arange(n_omega) * dom
+    err = e_inf(g.spectrum(), oracle_I(w, st, dirs=dirs, omegas=om))
+    assert err <= TOL
+
+
+def test_zero_and_fractional_weights(rad):
+    """N = 0 contributes nothing; 0 < N < 1 is a valid weighting (F^2 = N(1-g) + N^2 g)."""
+    w = SINGLE.scaled(n_particles=640, n_steps=2, nx_dir=4, ny_dir=4, n_omega=64, seed=33)
+    st = w.steps()
+    wts = np.random.default_rng(3).uniform(0.0, 1.0, w.n_particles)
+    wts[::5] = 0.0
+    st = dict(st)
+    st["w"] = np.broadcast_to(wts, st["w"].shape).copy()
+    I = run_gpu(rad, w, st).spectrum()
+    assert e_inf(I, oracle_I(w, st)) <= TOL
+    only_zero = dict(st)
+    only_zero["w"] = np.zeros_like(st["w"])
+    assert np.all(run_gpu(rad, w, only_zero).spectrum() == 0.0)
