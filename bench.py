@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 FLOPS_PER_UPDATE = 20          # complex rotate 6 + form-factor scale 2 + 3 complex FMAs 12
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector peak (published)
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E bandwidth (published)
 
 
 def parse():
@@ -35,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single_bunch_fp32",
                     choices=["single_bunch_fp32", "tiny_fp64", "batched_uneven", "serving", "precision_stress",
-                             "fig3_analogue"])
+                             "fig3_analogue", "tracked"])
     ap.add_argument("--time-steps", type=int, default=0, help="batched_uneven: override the 200 time steps")
     ap.add_argument("--skip-per-bunch", action="store_true", help="batched_uneven: time only the batched launch")
     ap.add_argument("--chunks", type=int, default=4000, help="serving: chunks in the arrival trace")
@@ -72,16 +73,17 @@ def calibrate_copy(mib: int) -> int:
     return 0
 
 
-def profiled_traffic(profile: str, tile: dict):
-    """HBM bytes per launch of the accumulate kernel from the committed rocprofv3 summary,
-    or None if the kernel source or the launch shape changed since those counters were taken."""
-    from paper_1802_03972_amd.build import accumulate_source_sha256
+def profiled_traffic(profile: str, tile: dict, files=None):
+    """HBM bytes per launch of the profiled kernel from the committed rocprofv3 summary, or
+    None if the kernel source (the accumulate sources unless `files` names others) or the
+    launch shape changed since those counters were taken."""
+    from paper_1802_03972_amd.build import ACCUMULATE_FILES, source_sha256
     if not tile:
         return None
     path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
-        sha = accumulate_source_sha256()
+        sha = source_sha256(files or ACCUMULATE_FILES)
     except OSError:
         return None
     vals = {}
@@ -89,7 +91,8 @@ def profiled_traffic(profile: str, tile: dict):
         if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "tile"):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    tile_s = ",".join(str(tile[k]) for k in ("w_per_lane", "dir_per_wave", "waves", "wg_per_cu"))
+    tile_s = (",".join(str(tile[k]) for k in ("w_per_lane", "dir_per_wave", "waves", "wg_per_cu"))
+              if isinstance(tile, dict) else str(tile))
     if vals.get("kernel_source_sha256") != sha or vals.get("tile") != tile_s or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
@@ -124,6 +127,8 @@ def main() -> int:
         return bench_precision(args)
     if args.workload == "fig3_analogue":
         return bench_fig3(args)
+    if args.workload == "tracked":
+        return bench_tracked(args)
 
     w = SINGLE if args.workload == "single_bunch_fp32" else TINY
     if args.shape:
@@ -566,6 +571,103 @@ def bench_precision(args) -> int:
                    "directions": w.n_dir, "frequencies": w.n_omega, "omega_max": w.omega_max, "input_dtype": "f64"},
         "modes": out_modes, "cpu_baseline": cpu,
         "input_rounding_single_bunch_fp32": input_rounding if use_oracle else None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_tracked(args) -> int:
+    """Post-processing variant: 1024 tracked particles x 100 steps of the single-bunch
+    generator on its 128 x 256 grid; each step adds every particle's term into its own FP64
+    time integral (read-modify-write of 32 B per particle and grid point), and the read-out
+    applies weights and shape afterwards.  Bound by HBM: 64 B per update."""
+    import numpy as np
+    import torch
+
+    import paper_1802_03972_amd as rad
+    from paper_1802_03972_amd.build import AUX_FILES
+    from workloads import SINGLE, flatten
+
+    w = SINGLE.scaled(n_particles=1024, n_steps=100, seed=7)
+    st = w.steps()
+    n = w.n_particles
+    dev = {k: torch.as_tensor(np.ascontiguousarray(st[k]).reshape(-1)).to("cuda:0", torch.float32)
+           for k in rad.FIELDS}
+    slices = [{k: v[j * n:(j + 1) * n] for k, v in dev.items()} for j in range(w.n_steps)]
+    times = w.times()
+    tr = rad.Tracked(w.directions(), w.omega0, w.domega, w.n_omega, n, dt=w.dt)
+    stream = torch.cuda.current_stream(0)
+    wts = st["w"][0]
+
+    def pushes():
+        tr.reset(stream)
+        for j in range(w.n_steps):
+            tr.push_step(float(times[j]), slices[j], stream)
+
+    for _ in range(max(1, args.warmup)):
+        pushes()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        pushes()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) * 1e-3)
+    updates = n * w.n_dir * w.n_omega * w.n_steps
+    value = updates * args.steps / elapsed
+    # per-launch duration of the accumulate kernel alone (events bracket only the pushes,
+    # one kernel each; the reset fill runs before ev0)
+    tr.reset(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for j in range(w.n_steps):
+        tr.push_step(float(times[j]), slices[j], stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / w.n_steps
+    bytes_per_launch = 64.0 * n * w.n_dir * w.n_omega
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    tc = time.perf_counter()
+    I = tr.spectrum(wts, w.shape, w.shape_len, stream)
+    readout_ms = (time.perf_counter() - tc) * 1e3
+    tile = "fixed: 256 threads, 16 frequencies per thread"   # the tracked kernel has one launch shape
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = len(os.sched_getaffinity(0))
+        oracle.set_threads(cores)
+        sel = np.arange(0, w.n_omega, 4)
+        tc = time.perf_counter()
+        Iref = oracle.spectrum(flatten(st, times), w.directions(), w.omegas()[sel], w.shape, w.shape_len, w.dt)
+        cpu_s = time.perf_counter() - tc
+        cu = n * w.n_steps * w.n_dir * len(sel)
+        cpu = {"value": cu / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"all {w.n_steps} steps x {n} particles x {w.n_dir} directions x every 4th of "
+                         f"{w.n_omega} frequencies ({cu:.3e} updates, {cpu_s:.1f} s)"}
+        parity = {"e_inf": float(np.max(np.abs(I[:, sel] - Iref)) / np.max(Iref)), "tolerance": 1e-4,
+                  "sample": "same as cpu_baseline"}
+        log(f"[bench] tracked parity on the sample: e_inf = {parity['e_inf']:.3e}")
+    tr.close()
+    log(f"[bench] tracked: {value:.4e} updates/s, {launch_ms:.4f} ms per step, {achieved:.0f} GB/s")
+    out = {
+        "metric": "particle*direction*frequency updates/s (vs FP32 peak); p50/p99 step latency",
+        "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup),
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tracked", "particles": n, "time_steps": w.n_steps, "directions": w.n_dir,
+                   "frequencies": w.n_omega, "shape_at_readout": w.shape, "integrals_bytes": 32 * n * w.n_dir * w.n_omega},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic("k_tracked_accumulate_tracked.md", tile, AUX_FILES),
+                     "kernel": "k_tracked_accumulate", "avg_launch_ms": round(launch_ms, 4),
+                     "bytes_per_update": 64},
+        "readout_ms": round(readout_ms, 3),
+        "cpu_baseline": cpu,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
     return 0

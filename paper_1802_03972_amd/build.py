@@ -25,14 +25,23 @@ HIPCC_FLAGS = [
 ]
 
 
-def accumulate_source_sha256() -> str:
-    """sha256 over the accumulate kernels' source files, in ACCUMULATE_FILES order."""
+# the files that define the auxiliary kernels (fold, read-out, tracked particles)
+AUX_FILES = ["rad_internal.h", "rad_device.h", "rad_kernels.hip"]
+
+
+def source_sha256(files) -> str:
+    """sha256 over the given csrc files, in order."""
     import hashlib
     h = hashlib.sha256()
-    for name in ACCUMULATE_FILES:
+    for name in files:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def accumulate_source_sha256() -> str:
+    """sha256 over the accumulate kernels' source files, in ACCUMULATE_FILES order."""
+    return source_sha256(ACCUMULATE_FILES)
 
 
 def hipcc() -> str:
