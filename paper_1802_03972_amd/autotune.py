@@ -132,18 +132,29 @@ def tune(n_dir: int, n_omega: int, dtype: str = "f32", precision: int = 0, n_par
         results.append((ms, c, ups))
         if verbose:
             print(f"  {c}: {ms:.4f} ms/push, {ups:.3e} updates/s", flush=True)
+    from . import device_cus
+    cus = device_cus(device)
     results = confirm(results, lambda c: measure(c, 4 * reps),
-                      lambda ms: n_particles * n_dir * n_omega / (ms * 1e-3), verbose)
+                      lambda ms: n_particles * n_dir * n_omega / (ms * 1e-3), verbose,
+                      traffic=lambda c: partial_bytes(c, n_dir, n_omega, cus))
     g.close()
     ms, best, ups = results[0]
     return {"tile": best, "ms_per_push": ms, "updates_per_s": ups, "n_particles": n_particles,
             "candidates": len(results), "measured_at": time.strftime("%Y-%m-%d")}
 
 
-def confirm(results, remeasure, rate, verbose: bool, top: int = 4):
+def partial_bytes(c: dict, n_dir: int, n_omega: int, cus: int) -> int:
+    """FP32 partial-tile bytes one launch writes (and its fold reads back): one
+    TD x TO x 16 B tile per workgroup, CUs x wg_per_cu workgroups."""
+    td, to = c["dir_per_wave"], c["waves"] * (64 // c["dir_per_wave"]) * c["w_per_lane"]
+    return cus * c["wg_per_cu"] * td * to * 16
+
+
+def confirm(results, remeasure, rate, verbose: bool, top: int = 4, traffic=None, tie: float = 0.01):
     """Second, longer pass over the fastest candidates of the sweep (single timings of a
     sub-millisecond push vary by a few per cent): re-time the best `top` and rank them by
-    the longer measurement."""
+    the longer measurement.  Among those within `tie` of the fastest, the one whose launch
+    writes the fewest partial-sum bytes (`traffic(c)`) goes first."""
     results = sorted(results, key=lambda r: r[0])
     again = []
     for ms0, c, _ in results[:top]:
@@ -152,6 +163,11 @@ def confirm(results, remeasure, rate, verbose: bool, top: int = 4):
         if verbose:
             print(f"  confirm {c}: {ms:.4f} ms (sweep {ms0:.4f})", flush=True)
     again.sort(key=lambda r: r[0])
+    if traffic is not None and again:
+        close = [r for r in again if r[0] <= again[0][0] * (1.0 + tie)]
+        pick = min(close, key=lambda r: traffic(r[1]))
+        again.remove(pick)
+        again.insert(0, pick)
     return again + results[top:]
 
 
@@ -202,7 +218,10 @@ def tune_batch(n_dir: int, n_omega: int, counts, dtype: str = "f32", precision: 
         results.append((ms, c, total / (ms * 1e-3)))
         if verbose:
             print(f"  batch {c}: {ms:.4f} ms/push, {total / (ms * 1e-3):.3e} updates/s", flush=True)
-    results = confirm(results, lambda c: measure(c, 3 * reps), lambda ms: total / (ms * 1e-3), verbose)
+    from . import device_cus
+    cus = device_cus(device)
+    results = confirm(results, lambda c: measure(c, 3 * reps), lambda ms: total / (ms * 1e-3), verbose,
+                      traffic=lambda c: partial_bytes(c, n_dir, n_omega, cus))
     b.close()
     for g in grids:
         g.close()

@@ -37,3 +37,18 @@ def test_variant_candidates_and_keys():
         assert cs and all(c["w_per_lane"] == 16 for c in cs)
         assert autotune.key(128, 256, 0, v).endswith(f":v{v}")
     assert autotune.key(128, 256, 0) == "128x256:p0"
+
+
+def test_confirm_prefers_less_partial_traffic_among_ties():
+    from paper_1802_03972_amd import autotune
+    a = {"w_per_lane": 16, "dir_per_wave": 16, "waves": 4, "wg_per_cu": 8}
+    b = {"w_per_lane": 16, "dir_per_wave": 32, "waves": 8, "wg_per_cu": 2}
+    c = {"w_per_lane": 32, "dir_per_wave": 32, "waves": 4, "wg_per_cu": 1}
+    times = {str(a): 0.4943, str(b): 0.4980, str(c): 0.60}
+    res = [(0.51, a, 0), (0.50, b, 0), (0.59, c, 0)]
+    tb = lambda x: autotune.partial_bytes(x, 128, 256, 256)
+    assert tb(b) < tb(a)
+    out = autotune.confirm(res, lambda x: times[str(x)], lambda ms: 1.0 / ms, False, traffic=tb)
+    assert out[0][1] == b                       # within 1 % of the fastest and half the bytes
+    out = autotune.confirm(res, lambda x: times[str(x)], lambda ms: 1.0 / ms, False, traffic=tb, tie=0.001)
+    assert out[0][1] == a                       # no tie: the fastest wins
