@@ -43,26 +43,46 @@ __global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
     double ph;
     particle_direction_setup<0, !DIRECT, 1>(raw, 0, a.dirs9 + 9 * d, a.domega, gv, ph, a.err);
     const int o0 = ob * W;
-    float zr = 1.f, zi = 0.f;
+    const int kmax = a.n_omega - o0 < W ? a.n_omega - o0 : W;
+    // the block's W phase factors first (recurrence or per-term FP64 phase) ...
+    float zr[W], zi[W];
     if constexpr (!DIRECT) {
         const double rv = frac_rev(a.omega[o0] * ph);
-        sincos_rev_fast(static_cast<float>(rv), zi, zr);
-    }
-    double* T = a.T + ((m * a.n_omega + o0) * a.n_dir + d) * 4;
-    for (int k = 0; k < W && o0 + k < a.n_omega; ++k, T += (int64_t)a.n_dir * 4) {
-        if constexpr (DIRECT) {
-            const double rv = frac_rev(a.omega[o0 + k] * ph);
-            sincos_rev_fast(static_cast<float>(rv), zi, zr);
+        sincos_rev_fast(static_cast<float>(rv), zi[0], zr[0]);
+#pragma unroll
+        for (int k = 1; k < W; ++k) {
+            zr[k] = fmaf(zr[k - 1], gv.z, -(zi[k - 1] * gv.w));
+            zi[k] = fmaf(zr[k - 1], gv.w, zi[k - 1] * gv.z);
         }
-        T[0] += (double)(gv.x * zr);
-        T[1] += (double)(gv.x * zi);
-        T[2] += (double)(gv.y * zr);
-        T[3] += (double)(gv.y * zi);
-        if constexpr (!DIRECT) {
-            const float nr = fmaf(zr, gv.z, -(zi * gv.w));
-            const float ni = fmaf(zr, gv.w, zi * gv.z);
-            zr = nr;
-            zi = ni;
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int kc = k < kmax ? k : kmax - 1;
+            const double rv = frac_rev(a.omega[o0 + kc] * ph);
+            sincos_rev_fast(static_cast<float>(rv), zi[k], zr[k]);
+        }
+    }
+    // ... then the read-modify-writes of the integrals, eight loads in flight before their
+    // stores (consecutive threads hold consecutive directions: 32 B each, contiguous)
+    constexpr int G = 8;
+    double4* T = reinterpret_cast<double4*>(a.T) + (m * a.n_omega + o0) * a.n_dir + d;
+    const int64_t stride = a.n_dir;
+#pragma unroll
+    for (int q = 0; q < W; q += G) {
+        double4 t[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            if (q + u < kmax) t[u] = T[(q + u) * stride];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int k = q + u;
+            if (k < kmax) {
+                t[u].x += (double)(gv.x * zr[k]);
+                t[u].y += (double)(gv.x * zi[k]);
+                t[u].z += (double)(gv.y * zr[k]);
+                t[u].w += (double)(gv.y * zi[k]);
+                T[k * stride] = t[u];
+            }
         }
     }
 }
