@@ -239,6 +239,16 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     }
 }
 
+// Block b runs on XCD b % 8; return its rank in XCD-major order: XCD 0's blocks first,
+// then XCD 1's, ...  For n blocks, XCD x holds n / 8 blocks, plus one if x < n % 8.
+__device__ __forceinline__ int xcd_major_id(int b, int n)
+{
+    constexpr int kXcd = 8;
+    const int per = n / kXcd, rem = n % kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 // Waves per SIMD the 16-frequency recurrence kernels (uniform grid, per-block step) are
 // compiled for: 4 caps them at 128 VGPRs, so four waves share a SIMD (the issue rate of
 // this VALU-bound loop grows with resident waves; the few spills this costs sit in the
@@ -265,8 +275,12 @@ __global__ void __launch_bounds__(512, min_waves(W, V)) k_accumulate(AccArgs a)
     constexpr int TD = DPW;
     const int TO = (blockDim.x >> 6) * (64 / DPW) * W;
     const int ntiles = a.job.tiles_d * a.job.tiles_w;
-    const int tile = blockIdx.x % ntiles;
-    const int split = blockIdx.x / ntiles;
+    // Workgroups are handed to the 8 XCDs round-robin; renumber them so that consecutive
+    // virtual ids -- the tiles of one particle split, which read the same particle chunk --
+    // run on one XCD and share its L2 (a bijection on [0, gridDim.x) whatever the policy).
+    const int v = xcd_major_id(blockIdx.x, gridDim.x);
+    const int tile = v % ntiles;
+    const int split = v / ntiles;
     const int td = tile % a.job.tiles_d;
     const int tw = tile / a.job.tiles_d;
     const int64_t n_local = a.job.i_end - a.job.i_begin;
