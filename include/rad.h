@@ -21,8 +21,11 @@
  *  - Return value: RAD_OK (0) or a negative RAD_ERR_* code; on error a message is
  *    available from rad_last_error() (per calling thread) and outputs are untouched.
  *  - `stream` is a hipStream_t passed as void*; NULL means the device's null stream.
- *    All work is stream-ordered.  Calls on one grid must be ordered on one stream (or
- *    synchronised by the caller); concurrent calls on one grid from several streams race.
+ *    All work is stream-ordered.  Calls on one grid come from one host thread at a time.
+ *    The library orders every update of a grid's accumulator itself (all folds run on
+ *    the grid's own stream, batched folds are chained into it, and read-outs wait for
+ *    the last fold), so pushes and read-outs may be issued on different streams; the
+ *    caller orders rad_reset / rad_set_state after pushes issued on other streams.
  *  - Device pointers are plain device addresses on the grid's device, caller-owned.
  *  - Units are SI: r [m], beta [1], dbeta/dt [1/s], N [electrons, real >= 0],
  *    t and dt [s], omega [rad/s], shape length [m].
