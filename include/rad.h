@@ -24,8 +24,8 @@
  *    All work is stream-ordered.  Calls on one grid come from one host thread at a time.
  *    The library orders every update of a grid's accumulator itself (all folds run on
  *    the grid's own stream, batched folds are chained into it, and read-outs wait for
- *    the last fold), so pushes and read-outs may be issued on different streams; the
- *    caller orders rad_reset / rad_set_state after pushes issued on other streams.
+ *    the last fold, resets are chained into it), so pushes, resets and read-outs may be
+ *    issued on different streams and take effect in the order they are issued.
  *  - Device pointers are plain device addresses on the grid's device, caller-owned.
  *  - Units are SI: r [m], beta [1], dbeta/dt [1/s], N [electrons, real >= 0],
  *    t and dt [s], omega [rad/s], shape length [m].

@@ -134,6 +134,7 @@ struct rad_grid {
     hipStream_t fold_stream = nullptr;
     hipEvent_t ev_acc_done[2] = {nullptr, nullptr};
     hipEvent_t ev_fold_done[2] = {nullptr, nullptr};
+    hipEvent_t ev_write = nullptr;   // end of a write of S on a caller's stream (reset)
     bool fold_recorded[2] = {false, false};
     int last_fold = -1;
     int* d_err = nullptr;
@@ -264,6 +265,7 @@ void free_grid(rad_grid* g)
         if (g->ev_acc_done[b]) (void)hipEventDestroy(g->ev_acc_done[b]);
         if (g->ev_fold_done[b]) (void)hipEventDestroy(g->ev_fold_done[b]);
     }
+    if (g->ev_write) (void)hipEventDestroy(g->ev_write);
     if (g->fold_stream) (void)hipStreamDestroy(g->fold_stream);
     if (g->d_err) (void)hipFree(g->d_err);
     if (g->d_out) (void)hipFree(g->d_out);
@@ -367,6 +369,19 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
 int after_folds(rad_grid* g, hipStream_t st)
 {
     if (g->last_fold >= 0) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[g->last_fold], 0));
+    return RAD_OK;
+}
+
+// S was just written on another stream up to `ev` (a batched fold, a reset): later folds,
+// which run on the grid's fold stream, and read-outs (which wait for the last fold event)
+// must come after it.  Chain the fold stream behind `ev` and move the last-fold mark there.
+int chain_fold_stream(rad_grid* g, hipEvent_t ev)
+{
+    RAD_HIP(hipStreamWaitEvent(g->fold_stream, ev, 0));
+    const int k = g->last_fold >= 0 ? g->last_fold : 0;
+    RAD_HIP(hipEventRecord(g->ev_fold_done[k], g->fold_stream));
+    g->fold_recorded[k] = true;
+    g->last_fold = k;
     return RAD_OK;
 }
 
@@ -558,7 +573,8 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
         hipEventCreateWithFlags(&g->ev_acc_done[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_acc_done[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_fold_done[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&g->ev_fold_done[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&g->ev_fold_done[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_write, hipEventDisableTiming) != hipSuccess) {
         free_grid(g);
         return fail(RAD_ERR_DEVICE, "cannot create the grid's fold stream and events");
     }
@@ -598,8 +614,9 @@ int rad_reset(rad_grid* g, void* stream)
     if (int rc0 = after_folds(g, st)) return rc0;
     hipError_t e = rad::launch_fill(g->d_S, (int64_t)g->n_dir * g->n_omega * 4, 0.0, st);
     if (e == hipSuccess) e = rad::launch_fill_int(g->d_err, 1, 0, st);
+    if (e == hipSuccess) e = hipEventRecord(g->ev_write, st);
     if (e != hipSuccess) return hip_fail(e, "reset");
-    return RAD_OK;
+    return chain_fold_stream(g, g->ev_write);
 }
 
 int rad_push_step(rad_grid* g, double t, int64_t n_particles, const rad_particles* p, void* stream)
@@ -1215,11 +1232,7 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
             rad_grid* g = in.grid;
             if (std::find(seen.begin(), seen.end(), g) != seen.end()) continue;
             seen.push_back(g);
-            RAD_HIP(hipStreamWaitEvent(g->fold_stream, last_done, 0));
-            const int k = g->last_fold >= 0 ? g->last_fold : 0;
-            RAD_HIP(hipEventRecord(g->ev_fold_done[k], g->fold_stream));
-            g->fold_recorded[k] = true;
-            g->last_fold = k;
+            if (int rc = chain_fold_stream(g, last_done)) return rc;
         }
     }
     return RAD_OK;

@@ -311,3 +311,22 @@ def test_zero_and_fractional_weights(rad):
     only_zero = dict(st)
     only_zero["w"] = np.zeros_like(st["w"])
     assert np.all(run_gpu(rad, w, only_zero).spectrum() == 0.0)
+
+
+def test_reset_push_readout_on_different_streams(rad):
+    """Accumulate, reset, accumulate again, read: four streams, no host synchronisation;
+    only the second accumulation may be in the result."""
+    import torch
+    w = SINGLE.scaled(n_particles=3000, n_steps=2, nx_dir=4, ny_dir=8, n_omega=128, seed=34)
+    st = w.steps()
+    other = SINGLE.scaled(n_particles=3000, n_steps=2, nx_dir=4, ny_dir=8, n_omega=128, seed=35).steps()
+    dev, dev_other = to_device(st, "f32"), to_device(other, "f32")
+    ref = make_grid(rad, w)
+    ref.push_steps(w.t0, w.n_steps, dev)
+    s1, s2, s3, s4 = (torch.cuda.Stream() for _ in range(4))
+    torch.cuda.synchronize()
+    g = make_grid(rad, w)
+    g.push_steps(w.t0, w.n_steps, dev_other, s1)
+    g.reset(s2)
+    g.push_steps(w.t0, w.n_steps, dev, s3)
+    assert e_inf(g.spectrum(s4), ref.spectrum()) <= 1e-6
