@@ -39,6 +39,8 @@ def parse():
                              "fig3_analogue", "tracked"])
     ap.add_argument("--time-steps", type=int, default=0, help="batched_uneven: override the 200 time steps")
     ap.add_argument("--skip-per-bunch", action="store_true", help="batched_uneven: time only the batched launch")
+    ap.add_argument("--skip-one-step", action="store_true",
+                    help="tracked: time only the multi-step push (no one-step comparison)")
     ap.add_argument("--chunks", type=int, default=4000, help="serving: chunks in the arrival trace")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: Poisson arrival rate [chunks/s]")
     ap.add_argument("--distinct-steps", type=int, default=8,
@@ -588,7 +590,10 @@ def bench_tracked(args) -> int:
     """Post-processing variant: 1024 tracked particles x 100 steps of the single-bunch
     generator on its 128 x 256 grid; each step adds every particle's term into its own FP64
     time integral (read-modify-write of 32 B per particle and grid point), and the read-out
-    applies weights and shape afterwards.  Bound by HBM: 64 B per update."""
+    applies weights and shape afterwards.  The timed push hands all 100 steps to one launch,
+    which sums 16 steps at a time in registers before each read-modify-write of the
+    integrals (64 B per particle and grid point per 16 steps); one-step pushes (64 B per
+    update, HBM-bound) are timed beside it."""
     import numpy as np
     import torch
 
@@ -609,8 +614,7 @@ def bench_tracked(args) -> int:
 
     def pushes():
         tr.reset(stream)
-        for j in range(w.n_steps):
-            tr.push_step(float(times[j]), slices[j], stream)
+        tr.push_steps(float(times[0]), w.n_steps, dev, stream)
 
     for _ in range(max(1, args.warmup)):
         pushes()
@@ -625,19 +629,29 @@ def bench_tracked(args) -> int:
     elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) * 1e-3)
     updates = n * w.n_dir * w.n_omega * w.n_steps
     value = updates * args.steps / elapsed
-    # per-launch duration of the accumulate kernel alone (events bracket only the pushes,
-    # one kernel each; the reset fill runs before ev0)
-    tr.reset(stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for j in range(w.n_steps):
-        tr.push_step(float(times[j]), slices[j], stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    launch_ms = e0.elapsed_time(e1) / w.n_steps
-    bytes_per_launch = 64.0 * n * w.n_dir * w.n_omega
-    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    # duration of the accumulate kernel alone: the 100-step push (one launch) and, for
+    # comparison, 100 one-step pushes (events bracket only the pushes; the reset fill runs
+    # before the first event)
+    def timed_push(multi):
+        tr.reset(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if multi:
+            tr.push_steps(float(times[0]), w.n_steps, dev, stream)
+        else:
+            for j in range(w.n_steps):
+                tr.push_step(float(times[j]), slices[j], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    single_ms = None if args.skip_one_step else timed_push(False) / w.n_steps
+    launch_ms = timed_push(True)
+    groups = -(-w.n_steps // 64)
+    points = n * w.n_dir * w.n_omega
+    bytes_per_launch = 64.0 * points * groups + 40.0 * n * w.n_steps
+    hbm = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    alu = points * w.n_steps * FLOPS_PER_UPDATE / (launch_ms * 1e-3) / 1e12
     tc = time.perf_counter()
     I = tr.spectrum(wts, w.shape, w.shape_len, stream)
     readout_ms = (time.perf_counter() - tc) * 1e3
@@ -660,7 +674,10 @@ def bench_tracked(args) -> int:
                   "sample": "same as cpu_baseline"}
         log(f"[bench] tracked parity on the sample: e_inf = {parity['e_inf']:.3e}")
     tr.close()
-    log(f"[bench] tracked: {value:.4e} updates/s, {launch_ms:.4f} ms per step, {achieved:.0f} GB/s")
+    log(f"[bench] tracked: {value:.4e} updates/s; 100-step push {launch_ms:.3f} ms ({hbm:.0f} GB/s, "
+        f"{alu:.1f} TFLOP/s)" + ("" if single_ms is None else
+                                  f"; one-step pushes {single_ms:.4f} ms each "
+                                  f"({64.0 * points / (single_ms * 1e-3) / 1e9:.0f} GB/s)"))
     out = {
         "metric": "particle*direction*frequency updates/s (vs FP32 peak); p50/p99 step latency",
         "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup),
@@ -668,11 +685,18 @@ def bench_tracked(args) -> int:
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "tracked", "particles": n, "time_steps": w.n_steps, "directions": w.n_dir,
                    "frequencies": w.n_omega, "shape_at_readout": w.shape, "integrals_bytes": 32 * n * w.n_dir * w.n_omega},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": ({"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(alu / FP32_PEAK_TFLOPS, 4)}
+                     if alu / FP32_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS else
+                     {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(hbm / HBM_PEAK_GBS, 4)}) | {
                      "traffic": profiled_traffic("k_tracked_accumulate_tracked.md", tile, AUX_FILES),
                      "kernel": "k_tracked_accumulate", "avg_launch_ms": round(launch_ms, 4),
-                     "bytes_per_update": 64},
+                     "algorithmic_hbm_GB_per_s": round(hbm, 1), "algorithmic_TFLOP_per_s": round(alu, 3),
+                     "bytes_per_launch": bytes_per_launch, "flops_per_update": FLOPS_PER_UPDATE},
+        "one_step_pushes": None if single_ms is None else {
+            "ms_per_push": round(single_ms, 4), "hbm_GB_per_s": round(64.0 * points / (single_ms * 1e-3) / 1e9, 1),
+            "updates_per_s": points / (single_ms * 1e-3)},
         "readout_ms": round(readout_ms, 3),
         "cpu_baseline": cpu,
         "parity": parity,

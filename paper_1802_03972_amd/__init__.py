@@ -425,6 +425,12 @@ class Tracked:
         _lib.check(_lib.lib().rad_tracked_push_step(self._h, float(t), ctypes.byref(p),
                                                     _stream_handle(stream, self.device)))
 
+    def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
+        """n_steps steps at t0 + j dt; arrays of n_steps * n_particles elements, step-major."""
+        p, n, keep = make_particles(particles, expect_len=int(n_steps) * self.n_particles, device=self.device)
+        _lib.check(_lib.lib().rad_tracked_push_steps(self._h, float(t0), int(n_steps), ctypes.byref(p),
+                                                     _stream_handle(stream, self.device)))
+
     def spectrum(self, weights, shape="cic", shape_len: float = 1e-7, stream=None) -> np.ndarray:
         w = np.ascontiguousarray(weights, np.float64).reshape(-1)
         if w.size != self.n_particles:

@@ -66,9 +66,12 @@ struct FoldJob {
 
 // Post-processing variant: one step of tracked particles into per-particle integrals.
 struct TrackedArgs {
-    const void* f[10];      // x, y, z, bx, by, bz, dbx, dby, dbz, w (w is not used)
+    const void* f[10];      // x, y, z, bx, by, bz, dbx, dby, dbz, w (w is not used);
+                            // n_steps x n_particles elements, step-major
     int64_t n_particles;
-    double t;
+    double t;               // time of the first step
+    double dt;              // step of the time grid (t_j = t + j dt)
+    int32_t n_steps;
     const double* dirs9;
     const double* omega;
     double domega;

@@ -21,8 +21,12 @@ namespace {
 // layout [m][omega][dir][4]; the form factor is applied only when the spectrum is read.
 // One thread per (particle, direction, block of W frequencies); geometry in FP64 as in the
 // main path; the block's frequencies follow the same rotation recurrence (or, for explicit
-// frequency lists, the per-term FP64 phase).
+// frequency lists, the per-term FP64 phase).  Up to kStepGroup steps of one push are summed
+// in FP32 registers before one read-modify-write of the FP64 integrals, so a multi-step
+// push moves 64 B per particle and grid point per group instead of per step.
 // ---------------------------------------------------------------------------------------
+constexpr int kStepGroup = 64;
+
 template <typename InT, bool DIRECT>
 __global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
 {
@@ -34,54 +38,65 @@ __global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
     const int ob = (int)(rest % n_blocks);
     const int64_t m = rest / n_blocks;
     if (m >= a.n_particles) return;
-    double raw[11];
-#pragma unroll
-    for (int f = 0; f < 9; ++f) raw[f] = load_wide<InT>(a.f[f], m);
-    raw[9] = 1.0;      // weights enter only at read-out; the weight field is never read
-    raw[10] = a.t;
-    float4 gv;
-    double ph;
-    particle_direction_setup<0, !DIRECT, 1>(raw, 0, a.dirs9 + 9 * d, a.domega, gv, ph, a.err);
     const int o0 = ob * W;
     const int kmax = a.n_omega - o0 < W ? a.n_omega - o0 : W;
-    // the block's W phase factors first (recurrence or per-term FP64 phase) ...
-    float zr[W], zi[W];
-    if constexpr (!DIRECT) {
-        const double rv = frac_rev(a.omega[o0] * ph);
-        sincos_rev_fast(static_cast<float>(rv), zi[0], zr[0]);
-#pragma unroll
-        for (int k = 1; k < W; ++k) {
-            zr[k] = fmaf(zr[k - 1], gv.z, -(zi[k - 1] * gv.w));
-            zi[k] = fmaf(zr[k - 1], gv.w, zi[k - 1] * gv.z);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const int kc = k < kmax ? k : kmax - 1;
-            const double rv = frac_rev(a.omega[o0 + kc] * ph);
-            sincos_rev_fast(static_cast<float>(rv), zi[k], zr[k]);
-        }
-    }
-    // ... then the read-modify-writes of the integrals, eight loads in flight before their
-    // stores (consecutive threads hold consecutive directions: 32 B each, contiguous)
+    const double om0 = a.omega[o0];
     constexpr int G = 8;
     double4* T = reinterpret_cast<double4*>(a.T) + (m * a.n_omega + o0) * a.n_dir + d;
     const int64_t stride = a.n_dir;
+    for (int j0 = 0; j0 < a.n_steps; j0 += kStepGroup) {
+        const int j1 = a.n_steps - j0 < kStepGroup ? a.n_steps : j0 + kStepGroup;
+        float4 acc[W];
 #pragma unroll
-    for (int q = 0; q < W; q += G) {
-        double4 t[G];
+        for (int k = 0; k < W; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int j = j0; j < j1; ++j) {
+            const int64_t i = (int64_t)j * a.n_particles + m;
+            double raw[11];
 #pragma unroll
-        for (int u = 0; u < G; ++u)
-            if (q + u < kmax) t[u] = T[(q + u) * stride];
+            for (int f = 0; f < 9; ++f) raw[f] = load_wide<InT>(a.f[f], i);
+            raw[9] = 1.0;      // weights enter only at read-out; the weight field is never read
+            raw[10] = a.t + (double)j * a.dt;
+            float4 gv;
+            double ph;
+            particle_direction_setup<0, !DIRECT, 1>(raw, 0, a.dirs9 + 9 * d, a.domega, gv, ph, a.err);
+            float zr = 1.f, zi = 0.f;
+            if constexpr (!DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int k = q + u;
-            if (k < kmax) {
-                t[u].x += (double)(gv.x * zr[k]);
-                t[u].y += (double)(gv.x * zi[k]);
-                t[u].z += (double)(gv.y * zr[k]);
-                t[u].w += (double)(gv.y * zi[k]);
-                T[k * stride] = t[u];
+            for (int k = 0; k < W; ++k) {
+                if constexpr (DIRECT) {
+                    const int kc = k < kmax ? k : kmax - 1;
+                    sincos_rev_fast(static_cast<float>(frac_rev(a.omega[o0 + kc] * ph)), zi, zr);
+                }
+                acc[k].x = fmaf(gv.x, zr, acc[k].x);
+                acc[k].y = fmaf(gv.x, zi, acc[k].y);
+                acc[k].z = fmaf(gv.y, zr, acc[k].z);
+                acc[k].w = fmaf(gv.y, zi, acc[k].w);
+                if constexpr (!DIRECT) {
+                    const float nr = fmaf(zr, gv.z, -(zi * gv.w));
+                    const float ni = fmaf(zr, gv.w, zi * gv.z);
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+        }
+        // read-modify-write of the integrals, eight loads in flight before their stores
+        // (consecutive threads hold consecutive directions: 32 B each, contiguous)
+#pragma unroll
+        for (int q = 0; q < W; q += G) {
+            double4 t[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (q + u < kmax) t[u] = T[(q + u) * stride];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int k = q + u;
+                if (k < kmax) {
+                    t[u].x += (double)acc[k].x;
+                    t[u].y += (double)acc[k].y;
+                    t[u].z += (double)acc[k].z;
+                    t[u].w += (double)acc[k].w;
+                    T[k * stride] = t[u];
+                }
             }
         }
     }

@@ -1420,11 +1420,15 @@ extern "C" int rad_tracked_reset(rad_tracked* tr, void* stream)
     return RAD_OK;
 }
 
-extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_particles* p, void* stream)
+namespace {
+
+int tracked_push(rad_tracked* tr, double t0, int32_t n_steps, const rad_particles* p, void* stream)
 {
     if (!tr) return fail(RAD_ERR_INVALID_ARG, "tracked is NULL");
-    if (!std::isfinite(t)) return fail(RAD_ERR_INVALID_ARG, "t is not finite");
+    if (!std::isfinite(t0)) return fail(RAD_ERR_INVALID_ARG, "t is not finite");
+    if (n_steps < 0) return fail(RAD_ERR_INVALID_ARG, "negative step count");
     if (!p) return fail(RAD_ERR_INVALID_ARG, "particles is NULL");
+    if (n_steps == 0) return RAD_OK;
     rad_particles q = *p;
     if (!q.w) q.w = q.x;   // the weight field is not read here
     int rc = check_particles(&q);
@@ -1435,7 +1439,9 @@ extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_partic
     a.f[3] = p->bx; a.f[4] = p->by; a.f[5] = p->bz;
     a.f[6] = p->dbx; a.f[7] = p->dby; a.f[8] = p->dbz; a.f[9] = nullptr;
     a.n_particles = tr->n_particles;
-    a.t = t;
+    a.t = t0;
+    a.dt = tr->dt;
+    a.n_steps = n_steps;
     a.dirs9 = tr->d_dirs9;
     a.omega = tr->d_omega;
     a.domega = tr->domega;
@@ -1446,6 +1452,19 @@ extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_partic
     hipError_t e = rad::launch_tracked_accumulate(a, p->dtype, tr->direct, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "tracked accumulate launch");
     return RAD_OK;
+}
+
+}  // namespace
+
+extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_particles* p, void* stream)
+{
+    return tracked_push(tr, t, 1, p, stream);
+}
+
+extern "C" int rad_tracked_push_steps(rad_tracked* tr, double t0, int32_t n_steps, const rad_particles* p,
+                                      void* stream)
+{
+    return tracked_push(tr, t0, n_steps, p, stream);
 }
 
 extern "C" int rad_tracked_spectrum(rad_tracked* tr, const double* weights_host, int32_t shape, double shape_len,

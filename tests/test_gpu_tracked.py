@@ -116,3 +116,20 @@ def test_errors(rad):
     with pytest.raises(rad.RadError) as ei:
         tr.spectrum(st["w"][0], "cic", w.shape_len)
     assert ei.value.code == rad.RAD_ERR_BAD_DATA
+
+
+@pytest.mark.parametrize("n_steps", [1, 16, 37])
+def test_multi_step_push(rad, n_steps):
+    """One push of several steps (summed 16 at a time in registers) equals per-step pushes
+    and the oracle."""
+    w = SINGLE.scaled(n_particles=256, n_steps=n_steps, nx_dir=4, ny_dir=4, n_omega=40, seed=47)
+    st = w.steps()
+    dev = to_device(st, "f32")
+    one = run_tracked(rad, w, st)
+    many = rad.Tracked(w.directions(), w.omega0, w.domega, w.n_omega, w.n_particles, dt=w.dt)
+    many.push_steps(w.t0, w.n_steps, dev)
+    I1 = one.spectrum(st["w"][0], w.shape, w.shape_len)
+    I2 = many.spectrum(st["w"][0], w.shape, w.shape_len)
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
+    assert e_inf(I2, I1) <= 1e-6
+    assert e_inf(I2, Iref) <= TOL
