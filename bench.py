@@ -591,8 +591,8 @@ def bench_tracked(args) -> int:
     generator on its 128 x 256 grid; each step adds every particle's term into its own FP64
     time integral (read-modify-write of 32 B per particle and grid point), and the read-out
     applies weights and shape afterwards.  The timed push hands all 100 steps to one launch,
-    which sums 16 steps at a time in registers before each read-modify-write of the
-    integrals (64 B per particle and grid point per 16 steps); one-step pushes (64 B per
+    which sums 64 steps at a time in registers before each read-modify-write of the
+    integrals (64 B per particle and grid point per 64 steps); one-step pushes (64 B per
     update, HBM-bound) are timed beside it."""
     import numpy as np
     import torch

@@ -118,9 +118,9 @@ def test_errors(rad):
     assert ei.value.code == rad.RAD_ERR_BAD_DATA
 
 
-@pytest.mark.parametrize("n_steps", [1, 16, 37])
+@pytest.mark.parametrize("n_steps", [1, 37, 150])
 def test_multi_step_push(rad, n_steps):
-    """One push of several steps (summed 16 at a time in registers) equals per-step pushes
+    """One push of several steps (summed 64 at a time in registers) equals per-step pushes
     and the oracle."""
     w = SINGLE.scaled(n_particles=256, n_steps=n_steps, nx_dir=4, ny_dir=4, n_omega=40, seed=47)
     st = w.steps()
