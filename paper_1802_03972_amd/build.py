@@ -75,7 +75,27 @@ def build(verbose: bool = False, extra_flags=()) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_c_demo(verbose)
     return LIB
+
+
+C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi", "rad_c_demo.c")
+C_DEMO = os.path.join(ROOT, "tests", "c_abi", "rad_c_demo")
+
+
+def build_c_demo(verbose: bool = False) -> str:
+    """The C-ABI test harness: plain C against include/rad.h, the HIP runtime and librad.so."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = C_DEMO + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+           "-I", os.path.join(rocm, "include"), C_DEMO_SRC, "-o", tmp, "-L", PKG, "-lrad",
+           f"-Wl,-rpath,{PKG}", "-Wl,-rpath,$ORIGIN/../../paper_1802_03972_amd",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, C_DEMO)
+    return C_DEMO
 
 
 if __name__ == "__main__":
