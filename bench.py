@@ -254,7 +254,8 @@ def main() -> int:
         cpu_updates = ns * n * w.n_dir * len(sel)
         cpu = {"value": cpu_updates / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"first {ns} of {w.n_steps} steps, all {n} particles, all {w.n_dir} directions, "
-                         f"every {kw}th of {w.n_omega} frequencies ({cpu_updates:.3e} updates, {cpu_s:.1f} s)"}
+                         f"every {kw}th of {w.n_omega} frequencies ({cpu_updates:.3e} updates, {cpu_s:.1f} s)",
+               "extrapolated_full_run_s": updates_per_step / (cpu_updates / cpu_s)}
         g.reset(stream)
         for j in range(ns):
             g.push_step(float(times[j]), slices[j], stream)
@@ -560,7 +561,8 @@ def bench_precision(args) -> int:
         upd = w.n_particles * n_steps * len(dsel) * len(osel)
         cpu = {"value": upd / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"all {n_steps} steps x {w.n_particles} particles, directions {dsel.tolist()}, "
-                         f"frequency indices {osel.tolist()} ({upd:.3e} updates, {cpu_s:.1f} s)"}
+                         f"frequency indices {osel.tolist()} ({upd:.3e} updates, {cpu_s:.1f} s)",
+               "extrapolated_full_run_s": w.n_particles * n_steps * w.n_dir * w.n_omega / (upd / cpu_s)}
         # input rounding of the FP32-input single-bunch workload: oracle on the FP64 trajectory
         # vs oracle on the FP32-rounded one (4 steps, every 16th frequency)
         ws = SINGLE.scaled(n_steps=4)
@@ -669,7 +671,8 @@ def bench_tracked(args) -> int:
         cu = n * w.n_steps * w.n_dir * len(sel)
         cpu = {"value": cu / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"all {w.n_steps} steps x {n} particles x {w.n_dir} directions x every 4th of "
-                         f"{w.n_omega} frequencies ({cu:.3e} updates, {cpu_s:.1f} s)"}
+                         f"{w.n_omega} frequencies ({cu:.3e} updates, {cpu_s:.1f} s)",
+               "extrapolated_full_run_s": n * w.n_steps * w.n_dir * w.n_omega / (cu / cpu_s)}
         parity = {"e_inf": float(np.max(np.abs(I[:, sel] - Iref)) / np.max(Iref)), "tolerance": 1e-4,
                   "sample": "same as cpu_baseline"}
         log(f"[bench] tracked parity on the sample: e_inf = {parity['e_inf']:.3e}")
