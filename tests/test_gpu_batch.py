@@ -196,3 +196,19 @@ def test_batch_then_single_pushes_on_other_streams(rad):
         r.push_steps(w.t0 + 5 * w.dt, w.n_steps, d)
     for a, r in zip(I, ref):
         assert e_inf(a, r.spectrum()) <= 1e-6
+
+
+def test_checkpoint_after_batched_push(rad):
+    """State saved after a batched push and restored into a fresh grid continues exactly
+    like the original grid."""
+    bs = bunches([1200, 500], steps=2)
+    grids = [grid_for(rad, w) for w, _ in bs]
+    devs = [to_device(st, "f32") for _, st in bs]
+    rad.Batcher().push([(g, w.t0, w.n_steps, d) for g, (w, _), d in zip(grids, bs, devs)])
+    w0, _ = bs[0]
+    saved = grids[0].get_state()
+    fresh = grid_for(rad, w0)
+    fresh.set_state(saved)
+    for g in (grids[0], fresh):
+        g.push_steps(w0.t0 + 7 * w0.dt, w0.n_steps, devs[0])
+    assert np.array_equal(grids[0].get_state(), fresh.get_state())
