@@ -33,6 +33,16 @@ def _stream_handle(stream, device: int):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _in_use_on(tensors, stream) -> None:
+    """Tell torch's caching allocator that `tensors` are read by work queued on `stream`
+    (when that is not the stream they were allocated on), so their memory is not handed out
+    again before that work has run."""
+    import torch
+    if isinstance(stream, torch.cuda.Stream):
+        for t in tensors:
+            t.record_stream(stream)
+
+
 def make_particles(fields: dict, expect_len: int | None = None, device: int | None = None):
     """Validate a dict of CUDA tensors and return (rad_particles, n, keepalive)."""
     import torch
@@ -127,6 +137,7 @@ class Grid:
         p, n, keep = make_particles(particles, device=self.device)
         _lib.check(_lib.lib().rad_push_step(self._h, float(t), n, ctypes.byref(p),
                                             _stream_handle(stream, self.device)))
+        _in_use_on(keep, stream)
 
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         p, n, keep = make_particles(particles, device=self.device)
@@ -134,6 +145,7 @@ class Grid:
             raise ValueError("particle arrays must hold n_steps * n_particles elements")
         _lib.check(_lib.lib().rad_push_steps(self._h, float(t0), int(n_steps), n // n_steps,
                                              ctypes.byref(p), _stream_handle(stream, self.device)))
+        _in_use_on(keep, stream)
 
     def reset(self, stream=None) -> None:
         _lib.check(_lib.lib().rad_reset(self._h, _stream_handle(stream, self.device)))
@@ -269,6 +281,8 @@ class Batcher:
                 raise ValueError("particle arrays must hold n_steps * n_particles elements")
             arr[k] = _lib.BatchItem(grid.handle.value, float(t0), int(n_steps), n // n_steps, p)
         _lib.check(_lib.lib().rad_batcher_push(self._h, arr, len(items), _stream_handle(stream, self.device)))
+        for ts in keep:
+            _in_use_on(ts, stream)
 
     def profile(self, enable: bool = True) -> None:
         _lib.check(_lib.lib().rad_batcher_profile_enable(self._h, 1 if enable else 0))
@@ -424,12 +438,14 @@ class Tracked:
         p, n, keep = make_particles(particles, expect_len=self.n_particles, device=self.device)
         _lib.check(_lib.lib().rad_tracked_push_step(self._h, float(t), ctypes.byref(p),
                                                     _stream_handle(stream, self.device)))
+        _in_use_on(keep, stream)
 
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         """n_steps steps at t0 + j dt; arrays of n_steps * n_particles elements, step-major."""
         p, n, keep = make_particles(particles, expect_len=int(n_steps) * self.n_particles, device=self.device)
         _lib.check(_lib.lib().rad_tracked_push_steps(self._h, float(t0), int(n_steps), ctypes.byref(p),
                                                      _stream_handle(stream, self.device)))
+        _in_use_on(keep, stream)
 
     def spectrum(self, weights, shape="cic", shape_len: float = 1e-7, stream=None) -> np.ndarray:
         w = np.ascontiguousarray(weights, np.float64).reshape(-1)
