@@ -148,6 +148,15 @@ def test_piecewise_uniform_list_batched(rad):
              for w in ws]
     devs = [to_device(st, "f32") for st in sts]
     rad.Batcher().push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
+    # the same batch replayed from a captured graph is bitwise equal, replay after replay
+    ref = [g.get_state() for g in grids]
+    gb = rad.Batcher(graph=True)
+    for _ in range(3):
+        for g in grids:
+            g.reset()
+        gb.push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
+        assert all(np.array_equal(g.get_state(), r) for g, r in zip(grids, ref))
+    assert gb.graph_stats()["launches"] >= 2
     for g, w, st, d in zip(grids, ws, sts, devs):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
         assert e_inf(g.spectrum(), Iref) <= TOL
