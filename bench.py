@@ -593,9 +593,9 @@ def bench_tracked(args) -> int:
     generator on its 128 x 256 grid; each step adds every particle's term into its own FP64
     time integral (read-modify-write of 32 B per particle and grid point), and the read-out
     applies weights and shape afterwards.  The timed push hands all 100 steps to one launch,
-    which sums 64 steps at a time in registers before each read-modify-write of the
-    integrals (64 B per particle and grid point per 64 steps); one-step pushes (64 B per
-    update, HBM-bound) are timed beside it."""
+    which sums up to `Tracked.step_group()` (128) steps in registers before each
+    read-modify-write of the integrals (64 B per particle and grid point per group);
+    one-step pushes (64 B per update, HBM-bound) are timed beside it."""
     import numpy as np
     import torch
 
@@ -649,15 +649,20 @@ def bench_tracked(args) -> int:
         return e0.elapsed_time(e1)
     single_ms = None if args.skip_one_step else timed_push(False) / w.n_steps
     launch_ms = timed_push(True)
-    groups = -(-w.n_steps // 64)
+    group = rad.Tracked.step_group()
+    groups = -(-w.n_steps // group)
     points = n * w.n_dir * w.n_omega
     bytes_per_launch = 64.0 * points * groups + 40.0 * n * w.n_steps
     hbm = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    alu = points * w.n_steps * FLOPS_PER_UPDATE / (launch_ms * 1e-3) / 1e12
+    # the tracked update has no form-factor scale (weights and shape enter at read-out):
+    # rotate 6 + three complex multiply-adds 12 = 18 flops in the 3-component form
+    flops = FLOPS_PER_UPDATE - 2
+    alu = points * w.n_steps * flops / (launch_ms * 1e-3) / 1e12
     tc = time.perf_counter()
     I = tr.spectrum(wts, w.shape, w.shape_len, stream)
     readout_ms = (time.perf_counter() - tc) * 1e3
-    tile = "fixed: 256 threads, 16 frequencies per thread"   # the tracked kernel has one launch shape
+    # the tracked kernel has one launch shape
+    tile = f"fixed: 256 threads, 16 frequencies per thread, {group}-step groups"
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -687,7 +692,8 @@ def bench_tracked(args) -> int:
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "tracked", "particles": n, "time_steps": w.n_steps, "directions": w.n_dir,
-                   "frequencies": w.n_omega, "shape_at_readout": w.shape, "integrals_bytes": 32 * n * w.n_dir * w.n_omega},
+                   "frequencies": w.n_omega, "shape_at_readout": w.shape, "integrals_bytes": 32 * n * w.n_dir * w.n_omega,
+                   "step_group": group},
         "roofline": ({"bound": "alu", "achieved": round(alu, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                       "frac": round(alu / FP32_PEAK_TFLOPS, 4)}
                      if alu / FP32_PEAK_TFLOPS >= hbm / HBM_PEAK_GBS else
@@ -696,7 +702,7 @@ def bench_tracked(args) -> int:
                      "traffic": profiled_traffic("k_tracked_accumulate_tracked.md", tile, AUX_FILES),
                      "kernel": "k_tracked_accumulate", "avg_launch_ms": round(launch_ms, 4),
                      "algorithmic_hbm_GB_per_s": round(hbm, 1), "algorithmic_TFLOP_per_s": round(alu, 3),
-                     "bytes_per_launch": bytes_per_launch, "flops_per_update": FLOPS_PER_UPDATE},
+                     "bytes_per_launch": bytes_per_launch, "flops_per_update": flops},
         "one_step_pushes": None if single_ms is None else {
             "ms_per_push": round(single_ms, 4), "hbm_GB_per_s": round(64.0 * points / (single_ms * 1e-3) / 1e9, 1),
             "updates_per_s": points / (single_ms * 1e-3)},

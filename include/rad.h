@@ -342,9 +342,13 @@ int rad_tracked_reset(rad_tracked* tr, void* stream);
 int rad_tracked_push_step(rad_tracked* tr, double t, const rad_particles* p, void* stream);
 
 /* n_steps steps at t0 + j dt (dt of the descriptor), device arrays of n_steps x
- * n_particles elements, step-major.  Up to 64 steps are summed in FP32 registers before
- * each update of the FP64 integrals, which cuts their HBM traffic by that factor. */
+ * n_particles elements, step-major.  Up to rad_tracked_step_group() steps are summed in
+ * FP32 registers before each update of the FP64 integrals, which cuts their HBM traffic by
+ * that factor. */
 int rad_tracked_push_steps(rad_tracked* tr, double t0, int32_t n_steps, const rad_particles* p, void* stream);
+
+/* Steps summed in registers per read-modify-write of the integrals (128). */
+int rad_tracked_step_group(void);
 
 /* Spectrum with the given HOST weights (n_particles, >= 0) and shape applied now;
  * I_host: n_dir x n_omega doubles.  Synchronises `stream`. */

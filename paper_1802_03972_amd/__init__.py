@@ -139,6 +139,11 @@ class Grid:
                                             _stream_handle(stream, self.device)))
         _in_use_on(keep, stream)
 
+    @staticmethod
+    def step_group() -> int:
+        """Steps one launch sums in registers per read-modify-write of the integrals."""
+        return int(_lib.lib().rad_tracked_step_group())
+
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         p, n, keep = make_particles(particles, device=self.device)
         if n_steps <= 0 or n % n_steps:
@@ -439,6 +444,11 @@ class Tracked:
         _lib.check(_lib.lib().rad_tracked_push_step(self._h, float(t), ctypes.byref(p),
                                                     _stream_handle(stream, self.device)))
         _in_use_on(keep, stream)
+
+    @staticmethod
+    def step_group() -> int:
+        """Steps one launch sums in registers per read-modify-write of the integrals."""
+        return int(_lib.lib().rad_tracked_step_group())
 
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         """n_steps steps at t0 + j dt; arrays of n_steps * n_particles elements, step-major."""

@@ -122,6 +122,7 @@ SIGNATURES = {
     "rad_tracked_reset": (ctypes.c_int, [_vp, _vp]),
     "rad_tracked_push_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.POINTER(Particles), _vp]),
     "rad_tracked_push_steps": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(Particles), _vp]),
+    "rad_tracked_step_group": (ctypes.c_int, []),
     "rad_tracked_spectrum": (ctypes.c_int, [_vp, _dp, ctypes.c_int32, ctypes.c_double, _dp, _vp]),
     "rad_debug_trig_probe": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
 }

@@ -19,83 +19,154 @@ namespace {
 // Post-processing variant: tracked particles keep their own time integral
 // T_m(n, omega) = sum_j A_{j,m}(n) exp(i omega tau_{j,m}) (no form factor) in FP64,
 // layout [m][omega][dir][4]; the form factor is applied only when the spectrum is read.
-// One thread per (particle, direction, block of W frequencies); geometry in FP64 as in the
-// main path; the block's frequencies follow the same rotation recurrence (or, for explicit
-// frequency lists, the per-term FP64 phase).  Up to kStepGroup steps of one push are summed
-// in FP32 registers before one read-modify-write of the FP64 integrals, so a multi-step
-// push moves 64 B per particle and grid point per group instead of per step.
+//
+// One workgroup of kTrackThreads threads per (particle, tile of TD directions x OB blocks of
+// W frequencies), OB = min(kTrackMaxOB, smallest power of two >= the number of frequency
+// blocks), TD = kTrackThreads / OB.  The steps of a push are taken S = OB at a time: the
+// S x TD (step, direction) geometries (FP64, as in the main path) are computed once, one per
+// thread, into LDS, then every thread walks its W frequencies for each of the S steps with
+// the rotation recurrence (or, for explicit frequency lists, the per-term FP64 phase).  The
+// per-(step, direction) set-up is thus shared by OB * W frequencies.  Up to kStepGroup steps
+// of one push are summed in FP32 registers before one read-modify-write of the FP64
+// integrals, so a multi-step push moves 64 B per particle and grid point per group instead
+// of per step (the main path likewise sums hundreds of particles in FP32 per partial).
 // ---------------------------------------------------------------------------------------
-constexpr int kStepGroup = 64;
+constexpr int kStepGroup = 128;
+constexpr int kTrackW = 16;
+constexpr int kTrackThreads = 256;
+constexpr int kTrackMaxOB = 16;
+
+struct TrackedTiling {
+    int ob;     // frequency blocks per workgroup (also the steps per sub-chunk)
+    int td;     // directions per workgroup
+    int n_dt;   // direction tiles
+    int n_ot;   // frequency tiles
+};
+
+__host__ __device__ inline TrackedTiling tracked_tiling(int n_dir, int n_omega)
+{
+    const int n_blocks = (n_omega + kTrackW - 1) / kTrackW;
+    int ob = 1;
+    while (ob < n_blocks && ob < kTrackMaxOB) ob *= 2;
+    TrackedTiling t;
+    t.ob = ob;
+    t.td = kTrackThreads / ob;
+    t.n_dt = (n_dir + t.td - 1) / t.td;
+    t.n_ot = (n_blocks + ob - 1) / ob;
+    return t;
+}
+
+// Waves per SIMD the tracked kernel is compiled for.  Capping it at 3 or 4 waves (168 or
+// 128 VGPRs) makes the compiler spill and measured 1.6-1.9x slower than 2.
+#ifndef RAD_TRACK_WAVES
+#define RAD_TRACK_WAVES 2
+#endif
 
 template <typename InT, bool DIRECT>
-__global__ void __launch_bounds__(256) k_tracked_accumulate(TrackedArgs a)
+__global__ void __launch_bounds__(kTrackThreads, RAD_TRACK_WAVES) k_tracked_accumulate(TrackedArgs a)
 {
-    constexpr int W = 16;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int W = kTrackW;
+    constexpr int SMAX = kTrackMaxOB;
+    __shared__ double raw[11 * SMAX];            // [field][step] of the sub-chunk
+    __shared__ float4 geo[kTrackThreads];        // [step][direction]: A1, A2, w
+    __shared__ double tau[kTrackThreads];        // [step][direction]: tau / (2 pi)
+    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega);
+    const int S = tl.ob, TD = tl.td;
+    const int tid = threadIdx.x;
+    int64_t b = blockIdx.x;
+    const int dt = (int)(b % tl.n_dt);
+    b /= tl.n_dt;
+    const int ot = (int)(b % tl.n_ot);
+    const int64_t m = b / tl.n_ot;               // grid: n_particles x n_ot x n_dt workgroups
+    const int dl = tid % TD;
+    const int d = dt * TD + dl;
+    const int dg = d < a.n_dir ? d : a.n_dir - 1;
     const int n_blocks = (a.n_omega + W - 1) / W;
-    const int d = (int)(idx % a.n_dir);
-    const int64_t rest = idx / a.n_dir;
-    const int ob = (int)(rest % n_blocks);
-    const int64_t m = rest / n_blocks;
-    if (m >= a.n_particles) return;
-    const int o0 = ob * W;
+    const int ob = ot * tl.ob + tid / TD;         // this thread's frequency block
+    const bool live = d < a.n_dir && ob < n_blocks;
+    const int o0 = (ob < n_blocks ? ob : n_blocks - 1) * W;
     const int kmax = a.n_omega - o0 < W ? a.n_omega - o0 : W;
     const double om0 = a.omega[o0];
+    double om[DIRECT ? W : 1];
+    if constexpr (DIRECT) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) om[k] = a.omega[o0 + (k < kmax ? k : kmax - 1)];
+    }
+    const int ss = tid / TD;                      // set-up role: step ss of the sub-chunk
     constexpr int G = 8;
     double4* T = reinterpret_cast<double4*>(a.T) + (m * a.n_omega + o0) * a.n_dir + d;
-    const int64_t stride = a.n_dir;
     for (int j0 = 0; j0 < a.n_steps; j0 += kStepGroup) {
         const int j1 = a.n_steps - j0 < kStepGroup ? a.n_steps : j0 + kStepGroup;
         float4 acc[W];
 #pragma unroll
         for (int k = 0; k < W; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int j = j0; j < j1; ++j) {
-            const int64_t i = (int64_t)j * a.n_particles + m;
-            double raw[11];
+        for (int js = j0; js < j1; js += S) {
+            const int ns = j1 - js < S ? j1 - js : S;
+            // 1. the particle's states at the sub-chunk's steps (step-major SoA input)
+            if (tid < ns) {
+                const int64_t i = (int64_t)(js + tid) * a.n_particles + m;
 #pragma unroll
-            for (int f = 0; f < 9; ++f) raw[f] = load_wide<InT>(a.f[f], i);
-            raw[9] = 1.0;      // weights enter only at read-out; the weight field is never read
-            raw[10] = a.t + (double)j * a.dt;
-            float4 gv;
-            double ph;
-            particle_direction_setup<0, !DIRECT, 1>(raw, 0, a.dirs9 + 9 * d, a.domega, gv, ph, a.err);
-            float zr = 1.f, zi = 0.f;
-            if constexpr (!DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
+                for (int f = 0; f < 9; ++f) raw[f * SMAX + tid] = load_wide<InT>(a.f[f], i);
+                raw[9 * SMAX + tid] = 1.0;     // weights enter only at read-out
+                raw[10 * SMAX + tid] = a.t + (double)(js + tid) * a.dt;
+            }
+            __syncthreads();
+            // 2. one (step, direction) geometry per thread
+            {
+                float4 gv = make_float4(0.f, 0.f, 1.f, 0.f);
+                double ph = 0.0;
+                if (ss < ns)
+                    particle_direction_setup<0, !DIRECT, SMAX>(raw, ss, a.dirs9 + 9 * dg, a.domega, gv, ph, a.err);
+                geo[tid] = gv;
+                tau[tid] = ph;
+            }
+            __syncthreads();
+            // 3. W frequencies per step; raw is rewritten only after every thread has passed
+            //    the barrier above, and geo/tau only after the next sub-chunk's first barrier
+            for (int s = 0; s < ns; ++s) {
+                const float4 gv = geo[s * TD + dl];
+                const double ph = tau[s * TD + dl];
+                float zr = 1.f, zi = 0.f;
+                if constexpr (!DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                if constexpr (DIRECT) {
-                    const int kc = k < kmax ? k : kmax - 1;
-                    sincos_rev_fast(static_cast<float>(frac_rev(a.omega[o0 + kc] * ph)), zi, zr);
-                }
-                acc[k].x = fmaf(gv.x, zr, acc[k].x);
-                acc[k].y = fmaf(gv.x, zi, acc[k].y);
-                acc[k].z = fmaf(gv.y, zr, acc[k].z);
-                acc[k].w = fmaf(gv.y, zi, acc[k].w);
-                if constexpr (!DIRECT) {
-                    const float nr = fmaf(zr, gv.z, -(zi * gv.w));
-                    const float ni = fmaf(zr, gv.w, zi * gv.z);
-                    zr = nr;
-                    zi = ni;
+                for (int k = 0; k < W; ++k) {
+                    if constexpr (DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om[k] * ph)), zi, zr);
+                    acc[k].x = fmaf(gv.x, zr, acc[k].x);
+                    acc[k].y = fmaf(gv.x, zi, acc[k].y);
+                    acc[k].z = fmaf(gv.y, zr, acc[k].z);
+                    acc[k].w = fmaf(gv.y, zi, acc[k].w);
+                    if constexpr (!DIRECT) {
+                        const float nr = fmaf(zr, gv.z, -(zi * gv.w));
+                        const float ni = fmaf(zr, gv.w, zi * gv.z);
+                        zr = nr;
+                        zi = ni;
+                    }
                 }
             }
         }
-        // read-modify-write of the integrals, eight loads in flight before their stores
-        // (consecutive threads hold consecutive directions: 32 B each, contiguous)
+        // 4. read-modify-write of the integrals, eight loads in flight before their stores
+        //    (consecutive threads hold consecutive directions: 32 B each, contiguous)
+        if (live) {
+            // an opaque copy of the stride keeps the W addresses from being hoisted out of
+            // the step-group loop (they would stay live through the hot loop)
+            int64_t stride = a.n_dir;
+            asm volatile("" : "+s"(stride));
 #pragma unroll
-        for (int q = 0; q < W; q += G) {
-            double4 t[G];
+            for (int q = 0; q < W; q += G) {
+                double4 t[G];
 #pragma unroll
-            for (int u = 0; u < G; ++u)
-                if (q + u < kmax) t[u] = T[(q + u) * stride];
+                for (int u = 0; u < G; ++u)
+                    if (q + u < kmax) t[u] = T[(q + u) * stride];
 #pragma unroll
-            for (int u = 0; u < G; ++u) {
-                const int k = q + u;
-                if (k < kmax) {
-                    t[u].x += (double)acc[k].x;
-                    t[u].y += (double)acc[k].y;
-                    t[u].z += (double)acc[k].z;
-                    t[u].w += (double)acc[k].w;
-                    T[k * stride] = t[u];
+                for (int u = 0; u < G; ++u) {
+                    const int k = q + u;
+                    if (k < kmax) {
+                        t[u].x += (double)acc[k].x;
+                        t[u].y += (double)acc[k].y;
+                        t[u].z += (double)acc[k].z;
+                        t[u].w += (double)acc[k].w;
+                        T[k * stride] = t[u];
+                    }
                 }
             }
         }
@@ -266,18 +337,22 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st)
     return hipGetLastError();
 }
 
+int tracked_step_group() { return kStepGroup; }
+
 hipError_t launch_tracked_accumulate(const TrackedArgs& a, int dtype, bool direct, hipStream_t st)
 {
-    const int64_t n_blocks = (a.n_omega + 15) / 16;
-    const int64_t threads = a.n_particles * n_blocks * a.n_dir;
-    if (threads <= 0) return hipSuccess;
-    const dim3 grid(grid1d(threads, 256));
+    if (a.n_particles <= 0 || a.n_steps <= 0 || a.n_dir <= 0 || a.n_omega <= 0) return hipSuccess;
+    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega);
+    const int64_t blocks = a.n_particles * tl.n_dt * tl.n_ot;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)blocks);
+    const dim3 block(kTrackThreads);
     if (dtype == 0) {
-        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<float, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_tracked_accumulate<float, false>), grid, dim3(256), 0, st, a);
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<float, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<float, false>), grid, block, 0, st, a);
     } else {
-        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<double, true>), grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_tracked_accumulate<double, false>), grid, dim3(256), 0, st, a);
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<double, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<double, false>), grid, block, 0, st, a);
     }
     return hipGetLastError();
 }

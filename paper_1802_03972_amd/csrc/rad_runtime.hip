@@ -1461,6 +1461,12 @@ extern "C" int rad_tracked_push_step(rad_tracked* tr, double t, const rad_partic
     return tracked_push(tr, t, 1, p, stream);
 }
 
+namespace rad {
+int tracked_step_group();   // rad_kernels.hip
+}
+
+extern "C" int rad_tracked_step_group(void) { return rad::tracked_step_group(); }
+
 extern "C" int rad_tracked_push_steps(rad_tracked* tr, double t0, int32_t n_steps, const rad_particles* p,
                                       void* stream)
 {

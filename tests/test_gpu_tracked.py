@@ -118,10 +118,12 @@ def test_errors(rad):
     assert ei.value.code == rad.RAD_ERR_BAD_DATA
 
 
-@pytest.mark.parametrize("n_steps", [1, 37, 150])
+@pytest.mark.parametrize("n_steps", [1, 37, 150, 300])
 def test_multi_step_push(rad, n_steps):
-    """One push of several steps (summed 64 at a time in registers) equals per-step pushes
-    and the oracle."""
+    """One push of several steps (summed up to 128 at a time in registers, in sub-chunks of
+    as many steps as the workgroup has frequency blocks) equals per-step pushes and the
+    oracle."""
+    assert rad.Tracked.step_group() == 128
     w = SINGLE.scaled(n_particles=256, n_steps=n_steps, nx_dir=4, ny_dir=4, n_omega=40, seed=47)
     st = w.steps()
     dev = to_device(st, "f32")
@@ -133,3 +135,26 @@ def test_multi_step_push(rad, n_steps):
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
     assert e_inf(I2, I1) <= 1e-6
     assert e_inf(I2, Iref) <= TOL
+
+
+@pytest.mark.parametrize("n_dir_xy,n_omega,omega_list", [((8, 8), 300, False), ((3, 5), 17, False),
+                                                         ((4, 8), 200, True)])
+def test_tracked_tiling(rad, n_dir_xy, n_omega, omega_list):
+    """Workgroup tilings of the tracked kernel: several direction and frequency tiles with
+    ragged ends (64 x 300: 16 directions x 16 frequency blocks per workgroup, the second
+    frequency tile partly empty; 15 x 17: 2 blocks, one of a single frequency; an explicit
+    log-spaced list), a 29-step push against the oracle."""
+    nx, ny = n_dir_xy
+    w = SINGLE.scaled(n_particles=96, n_steps=29, nx_dir=nx, ny_dir=ny, n_omega=n_omega, seed=48)
+    st = w.steps()
+    dev = to_device(st, "f32")
+    om = np.geomspace(1e15, 1e19, n_omega) if omega_list else None
+    tr = rad.Tracked(w.directions(), w.omega0, w.domega, w.n_omega, w.n_particles, dt=w.dt, omegas=om)
+    tr.push_steps(w.t0, w.n_steps, dev)
+    I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
+    omegas = om if omega_list else w.omegas()
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), omegas, w.shape, w.shape_len, w.dt)
+    err = e_inf(I, Iref)
+    print(f"tracked tiling {nx}x{ny} x {n_omega}: e_inf {err:.3e}")
+    assert I.shape == (nx * ny, n_omega)
+    assert err <= TOL
