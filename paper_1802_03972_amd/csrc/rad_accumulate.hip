@@ -20,8 +20,9 @@
 //        shared by the workgroup's TD directions;
 //     4. the hot loop: per particle, each lane seeds z = exp(i omega_first tau) from the
 //        FP64 phase (reduced to [0, 1) revolutions before leaving FP64), then walks its W
-//        frequencies with z <- z*w (uniform omega grid), scaling by F and accumulating.
-//        10 FP32 VALU operations per update: 2 (scale) + 4 (two complex FMAs) + 4 (rotate).
+//        frequencies with the three-term recurrence z_{k+1} = 2 cos(domega tau) z_k - z_{k-1}
+//        (uniform omega steps), scaling by F and accumulating.  8 FP32 VALU operations per
+//        update: 2 (scale) + 4 (two complex multiply-adds) + 2 (recurrence).
 // * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
 //   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
 
@@ -137,10 +138,13 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             float2 g = make_float2(0.f, 0.f);
             if (og < j.n_omega) g = j.gtab[og];
             float* dst = ff + o;
+            // the three-term recurrence carries x_k = sigma_k z_k (sigma = + + - - per 4
+            // frequencies); the weight carries the same sign so that F x_k = F_k z_k
+            const float sg = (!DIRECT && (o & 2)) ? -1.f : 1.f;
 #pragma unroll 8
             for (int m = 0; m < P; ++m, dst += TO) {
                 const float2 N = nw[m];
-                *dst = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
+                *dst = sg * __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
             }
         }
         __syncthreads();
@@ -171,10 +175,6 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     sincos_rev_fast(rw, wi, wr);
                 }
             }
-            // -Im(w) as its own register: the empty asm hides its origin, so the compiler
-            // cannot fold the sign back into a source modifier (a VOP3 encoding)
-            float nwi = -wi;
-            asm volatile("" : "+v"(nwi));
             const float4* fq = reinterpret_cast<const float4*>(ff + m * TO + ob * W);
             float Nm = 0.f, NN1 = 0.f;
             if constexpr (SHAPE3) {
@@ -182,45 +182,81 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 Nm = Nv.x;
                 NN1 = Nv.y - Nv.x;   // N^2 - N
             }
-#pragma unroll
-            for (int q = 0; q < W / 4; ++q) {
-                float Fv[4];
+            // the lane's weights for frequencies 4q .. 4q+3 (signed as the recurrence needs)
+            auto weights = [&](int q, float (&Fv)[4]) {
                 if constexpr (SHAPE3) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)   // F^2 = N + (N^2 - N) g(n, omega) (Eq. 12)
-                        Fv[u] = __builtin_amdgcn_sqrtf(fmaxf(fmaf(NN1, gl[4 * q + u], Nm), 0.f));
+                    for (int u = 0; u < 4; ++u) {   // F^2 = N + (N^2 - N) g(n, omega) (Eq. 12)
+                        const float f = __builtin_amdgcn_sqrtf(fmaxf(fmaf(NN1, gl[4 * q + u], Nm), 0.f));
+                        Fv[u] = (!DIRECT && (u & 2)) ? -f : f;
+                    }
                 } else {
                     const float4 F4 = fq[q];
                     Fv[0] = F4.x; Fv[1] = F4.y; Fv[2] = F4.z; Fv[3] = F4.w;
                 }
+            };
+            // S(k) += F A exp(i omega_k tau): 2 products and 4 multiply-adds
+            auto add = [&](int k, float F, float xr, float xi) {
+                const float ur = F * xr, ui = F * xi;
+                s1r[k] = fmaf(A1, ur, s1r[k]);
+                s1i[k] = fmaf(A1, ui, s1i[k]);
+                s2r[k] = fmaf(A2, ur, s2r[k]);
+                s2i[k] = fmaf(A2, ui, s2i[k]);
+            };
+            if constexpr (DIRECT) {
+                // explicit frequency list: each term's phase from the FP64 product, reduced to
+                // [0, 1) revolutions before leaving FP64
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int k = 4 * q + u;
-                    if constexpr (DIRECT) {
-                        // explicit frequency list: each term's phase from the FP64 product,
-                        // reduced to [0, 1) revolutions before leaving FP64
+                for (int q = 0; q < W / 4; ++q) {
+                    float Fv[4];
+                    weights(q, Fv);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = 4 * q + u;
                         if constexpr (PREC == 0) {
-                            const double rv = frac_rev(om[k] * ph);
-                            sincos_rev_fast(static_cast<float>(rv), zi, zr);
+                            sincos_rev_fast(static_cast<float>(frac_rev(om[k] * ph)), zi, zr);
                         } else {
                             float rv = (float)om[k] * (float)ph;
                             rv -= floorf(rv);
                             sincos_rev_fast(rv, zi, zr);
                         }
+                        add(k, Fv[u], zr, zi);
                     }
-                    const float ur = Fv[u] * zr;
-                    const float ui = Fv[u] * zi;
-                    s1r[k] = fmaf(A1, ur, s1r[k]);
-                    s1i[k] = fmaf(A1, ui, s1i[k]);
-                    s2r[k] = fmaf(A2, ur, s2r[k]);
-                    s2i[k] = fmaf(A2, ui, s2i[k]);
-                    if constexpr (!DIRECT) {
-                        // z <- z w with -Im(w) held negated, so that every operation is a
-                        // plain product or multiply-add (VOP2 encodings, no modifiers)
-                        const float nr = fmaf(zr, wr, zi * nwi);
-                        const float ni = fmaf(zr, wi, zi * wr);
-                        zr = nr;
-                        zi = ni;
+                }
+            } else {
+                // Uniform steps: the three-term recurrence z_{k+1} = 2 cos(theta) z_k - z_{k-1}
+                // (theta = domega tau), two multiply-adds per frequency instead of a complex
+                // product.  It runs on x_k = sigma_k z_k with sigma = (+, +, -, -) repeating,
+                // so that every step is a plain multiply-add into the older register,
+                // x_{k+1} = c_k x_k + x_{k-1}, c_k = 2 cos(theta) for even k and -2 cos(theta)
+                // for odd k; the weights carry sigma_k.  x_0 = z_0 comes from the FP64 phase,
+                // x_1 = z_0 w from one complex product.  Opaque negations (empty asm) keep every
+                // operation a VOP2 product or multiply-add without source modifiers.
+                float nwi = -wi;
+                asm volatile("" : "+v"(nwi));
+                const float cp = wr + wr;
+                float cn = -cp;
+                asm volatile("" : "+v"(cn));
+                float pr = zr, pi = zi;                                         // x_{k-1}
+                float qr = fmaf(zr, wr, zi * nwi), qi = fmaf(zr, wi, zi * wr);  // x_k, k = 1
+#pragma unroll
+                for (int q = 0; q < W / 4; ++q) {
+                    float Fv[4];
+                    weights(q, Fv);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int k = 4 * q + u;
+                        if (k == 0) {
+                            add(0, Fv[0], pr, pi);
+                            continue;
+                        }
+                        add(k, Fv[u], qr, qi);
+                        if (k + 1 < W) {
+                            const float ck = (k & 1) ? cn : cp;
+                            const float nr = fmaf(ck, qr, pr), ni = fmaf(ck, qi, pi);
+                            pr = qr; pi = qi;
+                            qr = nr; qi = ni;
+                        }
                     }
                 }
             }

@@ -25,8 +25,8 @@ namespace {
 // blocks), TD = kTrackThreads / OB.  The steps of a push are taken S = OB at a time: the
 // S x TD (step, direction) geometries (FP64, as in the main path) are computed once, one per
 // thread, into LDS, then every thread walks its W frequencies for each of the S steps with
-// the rotation recurrence (or, for explicit frequency lists, the per-term FP64 phase).  The
-// per-(step, direction) set-up is thus shared by OB * W frequencies.  Up to kStepGroup steps
+// the main path's three-term recurrence (or, for explicit frequency lists, the per-term
+// FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W frequencies.  Up to kStepGroup steps
 // of one push are summed in FP32 registers before one read-modify-write of the FP64
 // integrals, so a multi-step push moves 64 B per particle and grid point per group instead
 // of per step (the main path likewise sums hundreds of particles in FP32 per partial).
@@ -126,20 +126,41 @@ __global__ void __launch_bounds__(kTrackThreads, RAD_TRACK_WAVES) k_tracked_accu
             for (int s = 0; s < ns; ++s) {
                 const float4 gv = geo[s * TD + dl];
                 const double ph = tau[s * TD + dl];
-                float zr = 1.f, zi = 0.f;
-                if constexpr (!DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
+                auto add = [&](int k, float xr, float xi) {
+                    acc[k].x = fmaf(gv.x, xr, acc[k].x);
+                    acc[k].y = fmaf(gv.x, xi, acc[k].y);
+                    acc[k].z = fmaf(gv.y, xr, acc[k].z);
+                    acc[k].w = fmaf(gv.y, xi, acc[k].w);
+                };
+                if constexpr (DIRECT) {
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    if constexpr (DIRECT) sincos_rev_fast(static_cast<float>(frac_rev(om[k] * ph)), zi, zr);
-                    acc[k].x = fmaf(gv.x, zr, acc[k].x);
-                    acc[k].y = fmaf(gv.x, zi, acc[k].y);
-                    acc[k].z = fmaf(gv.y, zr, acc[k].z);
-                    acc[k].w = fmaf(gv.y, zi, acc[k].w);
-                    if constexpr (!DIRECT) {
-                        const float nr = fmaf(zr, gv.z, -(zi * gv.w));
-                        const float ni = fmaf(zr, gv.w, zi * gv.z);
-                        zr = nr;
-                        zi = ni;
+                    for (int k = 0; k < W; ++k) {
+                        float zr, zi;
+                        sincos_rev_fast(static_cast<float>(frac_rev(om[k] * ph)), zi, zr);
+                        add(k, zr, zi);
+                    }
+                } else {
+                    // the main path's three-term recurrence on x_k = sigma_k z_k, sigma =
+                    // (+, +, -, -) repeating; the sign is taken off when the sums are stored
+                    float zr, zi;
+                    sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
+                    float nwi = -gv.w;
+                    asm volatile("" : "+v"(nwi));
+                    const float cp = gv.z + gv.z;
+                    float cn = -cp;
+                    asm volatile("" : "+v"(cn));
+                    float pr = zr, pi = zi;                                             // x_{k-1}
+                    float qr = fmaf(zr, gv.z, zi * nwi), qi = fmaf(zr, gv.w, zi * gv.z);  // x_k, k = 1
+                    add(0, pr, pi);
+#pragma unroll
+                    for (int k = 1; k < W; ++k) {
+                        add(k, qr, qi);
+                        if (k + 1 < W) {
+                            const float ck = (k & 1) ? cn : cp;
+                            const float nr = fmaf(ck, qr, pr), ni = fmaf(ck, qi, pi);
+                            pr = qr; pi = qi;
+                            qr = nr; qi = ni;
+                        }
                     }
                 }
             }
@@ -161,10 +182,11 @@ __global__ void __launch_bounds__(kTrackThreads, RAD_TRACK_WAVES) k_tracked_accu
                 for (int u = 0; u < G; ++u) {
                     const int k = q + u;
                     if (k < kmax) {
-                        t[u].x += (double)acc[k].x;
-                        t[u].y += (double)acc[k].y;
-                        t[u].z += (double)acc[k].z;
-                        t[u].w += (double)acc[k].w;
+                        const double sg = (!DIRECT && (k & 2)) ? -1.0 : 1.0;
+                        t[u].x += sg * (double)acc[k].x;
+                        t[u].y += sg * (double)acc[k].y;
+                        t[u].z += sg * (double)acc[k].z;
+                        t[u].w += sg * (double)acc[k].w;
                         T[k * stride] = t[u];
                     }
                 }
