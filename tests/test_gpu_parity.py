@@ -330,3 +330,39 @@ def test_reset_push_readout_on_different_streams(rad):
     g.reset(s2)
     g.push_steps(w.t0, w.n_steps, dev, s3)
     assert e_inf(g.spectrum(s4), ref.spectrum()) <= 1e-6
+
+
+def test_recurrence_with_steps_near_zero_and_pi(rad):
+    """The three-term frequency recurrence loses the most accuracy when the per-frequency
+    phase step domega*tau is close to a multiple of pi (2 cos(theta) near +-2).  Particles
+    are placed so that on the axis the step is within 1e-7..1e-2 rad of 0 or pi (and within
+    ~0.02 rad of it on the tilted directions); three steps a whole number of step periods
+    apart."""
+    w = SINGLE.scaled(n_particles=2048, n_steps=3, n_omega=256, in_dtype="f64", seed=36)
+    C = 299792458.0
+    dom = w.domega
+    w = SINGLE.scaled(n_particles=2048, n_steps=3, n_omega=256, in_dtype="f64", seed=36,
+                      dt=7 * 2 * np.pi / dom)
+    rng = np.random.default_rng(36)
+    n = w.n_particles
+    eps = 10.0 ** rng.uniform(-7, -2, n) * rng.choice([-1.0, 1.0], n)
+    theta = 2 * np.pi * rng.integers(0, 6, n) + np.pi * rng.integers(0, 2, n) + eps
+    z = C * theta / dom
+    gamma = 200.0
+    beta = np.sqrt(1 - 1 / gamma**2)
+    bx, by = 1e-3 * rng.standard_normal(n), 1e-3 * rng.standard_normal(n)
+    bz = np.sqrt(beta**2 - bx**2 - by**2)
+    dbx, dby = 1e12 * rng.standard_normal(n), 1e12 * rng.standard_normal(n)
+    dbz = -(bx * dbx + by * dby) / bz
+    fields = dict(x=np.zeros(n), y=np.zeros(n), z=z, bx=bx, by=by, bz=bz, dbx=dbx, dby=dby, dbz=dbz,
+                  w=rng.uniform(1e3, 1e5, n))
+    st = {k: np.broadcast_to(v, (w.n_steps, n)).copy() for k, v in fields.items()}
+    tilt = np.array([0.0, 1e-4, 2e-3, 2e-2])
+    dirs = np.stack([tilt, np.zeros(4), np.sqrt(1 - tilt**2)], axis=1)
+    g = rad.Grid(dirs, w.omega0, dom, w.n_omega, shape=w.shape, shape_len=w.shape_len, dt=w.dt)
+    I = run_gpu(rad, w, st, grid=g).spectrum()
+    Iref = oracle_I(w, st, dirs=dirs)
+    err = e_inf(I, Iref)
+    per_dir = np.max(np.abs(I - Iref), axis=1) / np.max(Iref, axis=1)
+    print(f"near-degenerate steps: e_inf {err:.3e}, per direction {per_dir}")
+    assert err <= TOL and per_dir.max() <= TOL
