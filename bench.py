@@ -83,10 +83,11 @@ def calibrate_copy(mib: int) -> int:
     return 0
 
 
-def profiled_traffic(profile: str, tile: dict, files=None):
+def profiled_traffic(profile: str, tile: dict, files=None, suffix: str = ""):
     """HBM bytes per launch of the profiled kernel from the committed rocprofv3 summary, or
     None if the kernel source (the accumulate sources unless `files` names others) or the
-    launch shape changed since those counters were taken."""
+    launch shape changed since those counters were taken.  `suffix` selects one of several
+    entries of a summary (e.g. ".v1" for kernel variant 1)."""
     from paper_1802_03972_amd.build import ACCUMULATE_FILES, source_sha256
     if not tile:
         return None
@@ -98,9 +99,13 @@ def profiled_traffic(profile: str, tile: dict, files=None):
         return None
     vals = {}
     for line in text.splitlines():
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "tile"):
-            k, v = line.split(":", 1)
+        if ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        if k == "kernel_source_sha256":
             vals[k] = v.strip()
+        elif k in ("traffic_bytes_per_launch" + suffix, "tile" + suffix):
+            vals[k[:len(k) - len(suffix)]] = v.strip()
     tile_s = (",".join(str(tile[k]) for k in ("w_per_lane", "dir_per_wave", "waves", "wg_per_cu"))
               if isinstance(tile, dict) else str(tile))
     if vals.get("kernel_source_sha256") != sha or vals.get("tile") != tile_s or "traffic_bytes_per_launch" not in vals:
@@ -150,7 +155,6 @@ def main() -> int:
         from workloads import block_log_omegas
         om_list = block_log_omegas(1e-4 * w.omega_max, w.omega_max, w.n_omega)
     omegas = om_list if om_list is not None else w.omegas()
-    variant = bool(args.shape) or om_list is not None
     big = args.workload == "single_bunch_fp32"
     dev_id = 0
     torch.cuda.set_device(dev_id)
@@ -213,9 +217,12 @@ def main() -> int:
     achieved = upd_per_launch * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": profiled_traffic("k_accumulate_single_bunch_fp32.md", tile)
-                if big and not variant else None,
-                "traffic_source": "profiles/k_accumulate_single_bunch_fp32.md (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, bytes per launch)",
+                "traffic": (profiled_traffic("k_accumulate_single_bunch_fp32.md", tile) if not g.variant else
+                            profiled_traffic("k_accumulate_variants_single_bunch.md", tile, suffix=f".v{g.variant}"))
+                if big else None,
+                "traffic_source": ("profiles/k_accumulate_single_bunch_fp32.md" if not g.variant else
+                                   "profiles/k_accumulate_variants_single_bunch.md")
+                + " (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, bytes per launch)",
                 "kernel": "k_accumulate", "avg_launch_ms": round(avg_ms, 4),
                 "updates_per_launch": int(upd_per_launch), "flops_per_update": FLOPS_PER_UPDATE,
                 "fold_ms_per_launch": round(prof["fold_ms"] / max(1, prof["launches"]), 4)}
