@@ -669,7 +669,7 @@ def bench_tracked(args) -> int:
     I = tr.spectrum(wts, w.shape, w.shape_len, stream)
     readout_ms = (time.perf_counter() - tc) * 1e3
     # the tracked kernel has one launch shape
-    tile = f"fixed: 256 threads, 16 frequencies per thread, {group}-step groups"
+    tile = f"fixed: 256 threads, 8 frequencies per thread, {group}-step groups"
     cpu = None
     parity = None
     if not args.no_cpu_baseline:

@@ -21,20 +21,22 @@ namespace {
 // layout [m][omega][dir][4]; the form factor is applied only when the spectrum is read.
 //
 // One workgroup of kTrackThreads threads per (particle, tile of TD directions x OB blocks of
-// W frequencies), OB = min(kTrackMaxOB, smallest power of two >= the number of frequency
-// blocks), TD = kTrackThreads / OB.  The steps of a push are taken S = OB at a time: the
-// S x TD (step, direction) geometries (FP64, as in the main path) are computed once, one per
-// thread, into LDS, then every thread walks its W frequencies for each of the S steps with
-// the main path's three-term recurrence (or, for explicit frequency lists, the per-term
-// FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W frequencies.  Up to kStepGroup steps
-// of one push are summed in FP32 registers before one read-modify-write of the FP64
-// integrals, so a multi-step push moves 64 B per particle and grid point per group instead
-// of per step (the main path likewise sums hundreds of particles in FP32 per partial).
+// W = kTrackW frequencies), OB = min(kTrackMaxOB, smallest power of two >= the number of
+// frequency blocks), TD = kTrackThreads / OB.  The steps of a push are taken S = OB at a
+// time: the S x TD (step, direction) geometries (FP64, as in the main path) are computed
+// once, one per thread, into LDS, then every thread walks its W frequencies for each of the
+// S steps with the main path's three-term recurrence (or, for explicit frequency lists, the
+// per-term FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W
+// frequencies.  Up to kStepGroup steps of one push are summed in FP32 registers before one
+// read-modify-write of the FP64 integrals, so a multi-step push moves 64 B per particle and
+// grid point per group instead of per step (the main path likewise sums hundreds of
+// particles in FP32 per partial).  W = 8 (rather than 16) keeps the kernel at 162 VGPRs,
+// three waves per SIMD.
 // ---------------------------------------------------------------------------------------
 constexpr int kStepGroup = 128;
-constexpr int kTrackW = 16;
+constexpr int kTrackW = 8;
 constexpr int kTrackThreads = 256;
-constexpr int kTrackMaxOB = 16;
+constexpr int kTrackMaxOB = 256 / kTrackW;
 
 struct TrackedTiling {
     int ob;     // frequency blocks per workgroup (also the steps per sub-chunk)
@@ -56,10 +58,11 @@ __host__ __device__ inline TrackedTiling tracked_tiling(int n_dir, int n_omega)
     return t;
 }
 
-// Waves per SIMD the tracked kernel is compiled for.  Capping it at 3 or 4 waves (168 or
-// 128 VGPRs) makes the compiler spill and measured 1.6-1.9x slower than 2.
+// Waves per SIMD the tracked kernel is compiled for: three (at most 168 VGPRs; it needs 162
+// with 8 frequencies per thread).  More waves let one workgroup's read-modify-write of the
+// integrals overlap another's arithmetic; a four-wave cap spills and measured slower.
 #ifndef RAD_TRACK_WAVES
-#define RAD_TRACK_WAVES 2
+#define RAD_TRACK_WAVES 3
 #endif
 
 template <typename InT, bool DIRECT>

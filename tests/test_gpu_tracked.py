@@ -141,9 +141,9 @@ def test_multi_step_push(rad, n_steps):
                                                          ((4, 8), 200, True)])
 def test_tracked_tiling(rad, n_dir_xy, n_omega, omega_list):
     """Workgroup tilings of the tracked kernel: several direction and frequency tiles with
-    ragged ends (64 x 300: 16 directions x 16 frequency blocks per workgroup, the second
-    frequency tile partly empty; 15 x 17: 2 blocks, one of a single frequency; an explicit
-    log-spaced list), a 29-step push against the oracle."""
+    ragged ends (64 x 300: 38 frequency blocks, i.e. two frequency tiles, the second partly
+    empty, and several direction tiles; 15 x 17: three blocks, the last of a single
+    frequency; an explicit log-spaced list), a 29-step push against the oracle."""
     nx, ny = n_dir_xy
     w = SINGLE.scaled(n_particles=96, n_steps=29, nx_dir=nx, ny_dir=ny, n_omega=n_omega, seed=48)
     st = w.steps()
