@@ -370,6 +370,30 @@ def bench_batched(args) -> int:
     log(f"[bench] batched persistent, graph replays: {t_g * 1e3:.1f} ms per {n_steps} steps "
         f"({updates / t_g:.4e} updates/s), bitwise equal to direct: {graph_equal}, {gbatcher.graph_stats()}")
     agree = None if I_pb is None else max(float(np.max(np.abs(a - b)) / np.max(a)) for a, b in zip(I_pb, I_b))
+    # FP64 CPU oracle on the smallest bunch (all steps, every 2nd frequency), and the batched
+    # spectrum of that bunch against it
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from workloads import flatten
+        b = int(np.argmin([w.n_particles for w in ws]))
+        w = ws[b]
+        st = w.steps(0, kd)
+        full = {k: np.stack([st[k][j % kd] for j in range(n_steps)]) for k in st}
+        sel = np.arange(0, w.n_omega, 2)
+        cores = len(os.sched_getaffinity(0))
+        oracle.set_threads(cores)
+        tc = time.perf_counter()
+        Iref = oracle.spectrum(flatten(full, times[:n_steps]), w.directions(), w.omegas()[sel], w.shape,
+                               w.shape_len, w.dt)
+        cpu_s = time.perf_counter() - tc
+        cu = w.n_particles * n_steps * w.n_dir * len(sel)
+        cpu = {"value": cu / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"bunch {b} ({w.n_particles} particles), all {n_steps} steps, all {w.n_dir} directions, "
+                         f"every 2nd of {w.n_omega} frequencies ({cu:.3e} updates, {cpu_s:.1f} s)"}
+        parity = {"e_inf": float(np.max(np.abs(I_b[b][:, sel] - Iref)) / np.max(Iref)), "tolerance": 1e-4,
+                  "sample": "same as cpu_baseline (batched direct launches)"}
+        log(f"[bench] batched parity on the sample: e_inf = {parity['e_inf']:.3e}")
     avg_ms = prof["accumulate_ms"] / max(1, prof["launches"])
     achieved = prof["updates"] / max(1, prof["launches"]) * FLOPS_PER_UPDATE / (avg_ms * 1e-3) / 1e12
     out = {
@@ -392,6 +416,8 @@ def bench_batched(args) -> int:
                                        "scaled by the copy-kernel calibration, bytes per launch)",
                      "kernel": "k_accumulate_batch", "avg_launch_ms": round(avg_ms, 4),
                      "fold_ms_per_launch": round(prof["fold_ms"] / max(1, prof["launches"]), 4)},
+        "cpu_baseline": cpu,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -423,6 +449,7 @@ def bench_serving(args) -> int:
     per_chunk_updates = np.array([w.n_particles * w.n_dir * w.n_omega for w in ws], dtype=np.float64)
 
     server_tile = []
+    served_steps = []
 
     def run(rate, n_chunks, seed):
         arrivals, which = poisson_trace(rate, n_chunks, len(ws), seed=seed)
@@ -454,6 +481,7 @@ def bench_serving(args) -> int:
             done.append(s["t_complete"])
             bsz.append(s["batch_size"])
         server_tile.append(srv.get_tile())
+        served_steps.append(list(step_of))
         srv.close()
         total = float(sum(per_chunk_updates[b] for _, b, _ in tickets))
         span = max(done) - (t0 + arrivals[0])
@@ -467,6 +495,35 @@ def bench_serving(args) -> int:
 
     full = run(args.rate, args.chunks, seed=0)
     log(f"[bench] serving at {args.rate:.0f}/s: {full}")
+    # FP64 CPU oracle on the smallest bunch's served steps (16 directions x every 32nd
+    # frequency), and its served spectrum against it (read before the load-scaled runs add
+    # to the same grids)
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from workloads import flatten
+        b = int(np.argmin([w.n_particles for w in ws]))
+        w = ws[b]
+        n_b = served_steps[0][b]
+        st = w.steps(0, kd)
+        stf = {k: np.stack([st[k][j % kd].astype(np.float32).astype(np.float64) for j in range(n_b)]) for k in st}
+        dsel = np.arange(0, w.n_dir, max(1, w.n_dir // 16))
+        osel = np.arange(0, w.n_omega, 32)
+        cores = len(os.sched_getaffinity(0))
+        oracle.set_threads(cores)
+        tc = time.perf_counter()
+        Iref = oracle.spectrum(flatten(stf, np.arange(n_b, dtype=np.float64) * w.dt), w.directions()[dsel],
+                               w.omegas()[osel], w.shape, w.shape_len, w.dt)
+        cpu_s = time.perf_counter() - tc
+        cu = w.n_particles * n_b * len(dsel) * len(osel)
+        cpu = {"value": cu / cpu_s, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"bunch {b} ({w.n_particles} particles), its {n_b} served steps, {len(dsel)} of "
+                         f"{w.n_dir} directions x {len(osel)} of {w.n_omega} frequencies ({cu:.3e} updates, "
+                         f"{cpu_s:.1f} s)"}
+        I = grids[b].spectrum()[np.ix_(dsel, osel)]
+        parity = {"e_inf": float(np.max(np.abs(I - Iref)) / np.max(Iref)), "tolerance": 1e-4,
+                  "sample": "same as cpu_baseline (served spectrum of that bunch)"}
+        log(f"[bench] serving parity on the sample: e_inf = {parity['e_inf']:.3e}")
     cap = full["achieved_updates_per_s"] / per_chunk_updates.mean()
     scaled = []
     for f in (0.5, 0.8):
@@ -485,6 +542,8 @@ def bench_serving(args) -> int:
         "latency_ms": {"p50": full["p50_ms"], "p99": full["p99_ms"], "unit": "ms",
                        "what": "chunk arrival to completion"},
         "serving": full, "load_scaled": scaled,
+        "cpu_baseline": cpu,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
     return 0
