@@ -81,3 +81,21 @@ def test_valid_request_without_a_gpu_fails_loudly(L):
     rc = L.rad_create_grid(ctypes.byref(h), ctypes.byref(desc(ONE)))
     assert rc == _lib.RAD_ERR_DEVICE and not h.value
     assert L.rad_last_error().decode()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 (or a multi-rank launch) exits with status 2
+    and says why, before touching the device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, WORLD_SIZE="1")
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, env=env, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
+    env["WORLD_SIZE"] = "4"
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py")], capture_output=True, text=True, env=env,
+                       timeout=120)
+    assert r.returncode == 2 and "WORLD_SIZE 4" in r.stderr
