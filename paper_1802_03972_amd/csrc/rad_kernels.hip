@@ -20,9 +20,9 @@ namespace {
 // T_m(n, omega) = sum_j A_{j,m}(n) exp(i omega tau_{j,m}) (no form factor) in FP64,
 // layout [m][omega][dir][4]; the form factor is applied only when the spectrum is read.
 //
-// One workgroup of kTrackThreads threads per (particle, tile of TD directions x OB blocks of
-// W = kTrackW frequencies), OB = min(kTrackMaxOB, smallest power of two >= the number of
-// frequency blocks), TD = kTrackThreads / OB.  The steps of a push are taken S = OB at a
+// One workgroup of NT threads per (particle, tile of TD directions x OB blocks of
+// W = kTrackW frequencies), OB = min(NT / W, smallest power of two >= the number of
+// frequency blocks), TD = NT / OB.  The steps of a push are taken S = OB at a
 // time: the S x TD (step, direction) geometries (FP64, as in the main path) are computed
 // once, one per thread, into LDS, then every thread walks its W frequencies for each of the
 // S steps with the main path's three-term recurrence (or, for explicit frequency lists, the
@@ -35,8 +35,11 @@ namespace {
 // ---------------------------------------------------------------------------------------
 constexpr int kStepGroup = 128;
 constexpr int kTrackW = 8;
+// Workgroup sizes: 256 threads for multi-step pushes, 512 for one-step pushes (measured:
+// 512 is 7 % faster on one-step pushes, whose workgroups mostly wait for their integrals,
+// and 42 % slower on a 100-step push).
 constexpr int kTrackThreads = 256;
-constexpr int kTrackMaxOB = 256 / kTrackW;
+constexpr int kTrackThreadsOneStep = 512;
 
 struct TrackedTiling {
     int ob;     // frequency blocks per workgroup (also the steps per sub-chunk)
@@ -45,14 +48,15 @@ struct TrackedTiling {
     int n_ot;   // frequency tiles
 };
 
-__host__ __device__ inline TrackedTiling tracked_tiling(int n_dir, int n_omega)
+__host__ __device__ inline TrackedTiling tracked_tiling(int n_dir, int n_omega, int nt)
 {
+    const int max_ob = nt / kTrackW;
     const int n_blocks = (n_omega + kTrackW - 1) / kTrackW;
     int ob = 1;
-    while (ob < n_blocks && ob < kTrackMaxOB) ob *= 2;
+    while (ob < n_blocks && ob < max_ob) ob *= 2;
     TrackedTiling t;
     t.ob = ob;
-    t.td = kTrackThreads / ob;
+    t.td = nt / ob;
     t.n_dt = (n_dir + t.td - 1) / t.td;
     t.n_ot = (n_blocks + ob - 1) / ob;
     return t;
@@ -65,15 +69,15 @@ __host__ __device__ inline TrackedTiling tracked_tiling(int n_dir, int n_omega)
 #define RAD_TRACK_WAVES 3
 #endif
 
-template <typename InT, bool DIRECT>
-__global__ void __launch_bounds__(kTrackThreads, RAD_TRACK_WAVES) k_tracked_accumulate(TrackedArgs a)
+template <typename InT, bool DIRECT, int NT>
+__global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(TrackedArgs a)
 {
     constexpr int W = kTrackW;
-    constexpr int SMAX = kTrackMaxOB;
+    constexpr int SMAX = NT / kTrackW;
     __shared__ double raw[11 * SMAX];            // [field][step] of the sub-chunk
-    __shared__ float4 geo[kTrackThreads];        // [step][direction]: A1, A2, w
-    __shared__ double tau[kTrackThreads];        // [step][direction]: tau / (2 pi)
-    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega);
+    __shared__ float4 geo[NT];                   // [step][direction]: A1, A2, w
+    __shared__ double tau[NT];                   // [step][direction]: tau / (2 pi)
+    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega, NT);
     const int S = tl.ob, TD = tl.td;
     const int tid = threadIdx.x;
     int64_t b = blockIdx.x;
@@ -364,22 +368,29 @@ hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st)
 
 int tracked_step_group() { return kStepGroup; }
 
-hipError_t launch_tracked_accumulate(const TrackedArgs& a, int dtype, bool direct, hipStream_t st)
+template <int NT>
+hipError_t launch_tracked_nt(const TrackedArgs& a, int dtype, bool direct, hipStream_t st)
 {
-    if (a.n_particles <= 0 || a.n_steps <= 0 || a.n_dir <= 0 || a.n_omega <= 0) return hipSuccess;
-    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega);
+    const TrackedTiling tl = tracked_tiling(a.n_dir, a.n_omega, NT);
     const int64_t blocks = a.n_particles * tl.n_dt * tl.n_ot;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks);
-    const dim3 block(kTrackThreads);
+    const dim3 block(NT);
     if (dtype == 0) {
-        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<float, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_tracked_accumulate<float, false>), grid, block, 0, st, a);
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<float, true, NT>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<float, false, NT>), grid, block, 0, st, a);
     } else {
-        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<double, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_tracked_accumulate<double, false>), grid, block, 0, st, a);
+        if (direct) hipLaunchKernelGGL((k_tracked_accumulate<double, true, NT>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_tracked_accumulate<double, false, NT>), grid, block, 0, st, a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_tracked_accumulate(const TrackedArgs& a, int dtype, bool direct, hipStream_t st)
+{
+    if (a.n_particles <= 0 || a.n_steps <= 0 || a.n_dir <= 0 || a.n_omega <= 0) return hipSuccess;
+    return a.n_steps == 1 ? launch_tracked_nt<kTrackThreadsOneStep>(a, dtype, direct, st)
+                          : launch_tracked_nt<kTrackThreads>(a, dtype, direct, st);
 }
 
 hipError_t launch_tracked_finalize(const double* T, const double* wts, const double* gk, const double* g3,
