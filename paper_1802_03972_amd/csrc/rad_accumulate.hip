@@ -31,6 +31,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "rad_device.h"
@@ -353,18 +354,35 @@ __global__ void __launch_bounds__(512, min_waves(W, V)) k_accumulate_batch(const
     }
 }
 
+// Raises `kern`'s dynamic-LDS limit to `lds` bytes on the current device if it needs more
+// than the default 64 KiB.  The attribute is set per device; `allowed` caches, per device
+// ordinal, the largest limit already set (safe for concurrent callers: at worst two of them
+// set the same attribute).
+constexpr int kMaxDevices = 64;
+inline hipError_t allow_lds(const void* kern, size_t lds, std::atomic<size_t>* allowed)
+{
+    if (lds <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const bool cached = dev >= 0 && dev < kMaxDevices;
+    if (cached && lds <= allowed[dev].load(std::memory_order_acquire)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess || !cached) return e;
+    size_t cur = allowed[dev].load(std::memory_order_relaxed);
+    while (cur < lds && !allowed[dev].compare_exchange_weak(cur, lds, std::memory_order_release)) {
+    }
+    return hipSuccess;
+}
+
 template <typename InT, int PREC, int W, int DPW, int V>
 hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
 {
     auto kern = k_accumulate<InT, PREC, W, DPW, V>;
     const size_t lds = acc_lds_bytes(s);
-    static size_t lds_allowed = 64 * 1024;  // per instantiation; the attribute is process-wide
-    if (lds > lds_allowed) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_allowed = lds;
-    }
+    static std::atomic<size_t> lds_allowed[kMaxDevices] = {};   // per instantiation and device
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_allowed);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, a);
     return hipGetLastError();
 }
@@ -382,13 +400,9 @@ hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks
 {
     auto kern = k_accumulate_batch<InT, PREC, W, DPW, V>;
     const size_t lds = acc_lds_bytes(s);
-    static size_t lds_allowed = 64 * 1024;
-    if (lds > lds_allowed) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        lds_allowed = lds;
-    }
+    static std::atomic<size_t> lds_allowed[kMaxDevices] = {};   // per instantiation and device
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_allowed);
+    if (e != hipSuccess) return e;
     if (b.prepare_only) return hipSuccess;
     hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, b.items, b.wg_seg_begin,
                        b.segs, b.seg_part);
