@@ -137,20 +137,26 @@ def test_multi_step_push(rad, n_steps):
     assert e_inf(I2, Iref) <= TOL
 
 
+@pytest.mark.parametrize("per_step", [False, True])
 @pytest.mark.parametrize("n_dir_xy,n_omega,omega_list", [((8, 8), 300, False), ((3, 5), 17, False),
                                                          ((4, 8), 200, True)])
-def test_tracked_tiling(rad, n_dir_xy, n_omega, omega_list):
+def test_tracked_tiling(rad, n_dir_xy, n_omega, omega_list, per_step):
     """Workgroup tilings of the tracked kernel: several direction and frequency tiles with
     ragged ends (64 x 300: 38 frequency blocks, i.e. two frequency tiles, the second partly
     empty, and several direction tiles; 15 x 17: three blocks, the last of a single
-    frequency; an explicit log-spaced list), a 29-step push against the oracle."""
+    frequency; an explicit log-spaced list), a 29-step push (or 29 one-step pushes, which use
+    larger workgroups) against the oracle."""
     nx, ny = n_dir_xy
     w = SINGLE.scaled(n_particles=96, n_steps=29, nx_dir=nx, ny_dir=ny, n_omega=n_omega, seed=48)
     st = w.steps()
     dev = to_device(st, "f32")
     om = np.geomspace(1e15, 1e19, n_omega) if omega_list else None
     tr = rad.Tracked(w.directions(), w.omega0, w.domega, w.n_omega, w.n_particles, dt=w.dt, omegas=om)
-    tr.push_steps(w.t0, w.n_steps, dev)
+    if per_step:
+        for j, t in enumerate(w.times()):
+            tr.push_step(float(t), step_slice(dev, j, w.n_particles))
+    else:
+        tr.push_steps(w.t0, w.n_steps, dev)
     I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
     omegas = om if omega_list else w.omegas()
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), omegas, w.shape, w.shape_len, w.dt)
