@@ -101,6 +101,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     }
 
     for (int64_t c = c_begin; c < c_end; ++c) {
+        // Stages 1-3 gate the workgroup's barriers: their waves get issue priority over the
+        // hot loops of other workgroups on the CU (measured +2 %); the hot loop runs at the
+        // normal priority.
+        __builtin_amdgcn_s_setprio(2);
         // 1. stage the chunk (SoA, coalesced), widened to FP64, plus the step time.
         if (tid < P) {
             const int64_t i = j.i_begin + c * P + tid;
@@ -149,6 +153,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             }
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         // 4. hot loop.
         for (int m = 0; m < P; ++m) {
             const float4 gm = geo[m * TD + dl];
