@@ -103,8 +103,13 @@ typedef struct rad_particles {
     const void *w;                 /* weighting N (electrons per macro-particle)       */
 } rad_particles;
 
-/* Create a grid: copies the directions, builds the frequency and shape tables and a
- * zeroed FP64 accumulator on `d->device`.  *out is written only on success. */
+/* Create a grid: the observation points (n, omega) on which Eq. 13 (Sec. 3.3) is
+ * evaluated -- every direction n of the far-field sum of Eq. 1 (Sec. 2) paired with every
+ * frequency omega -- with the macro-particle shape whose normalised Table 1 factor g(omega)
+ * enters F_m of Eqs. 11-12.  Copies the directions, builds the frequency and shape tables
+ * and a zeroed FP64 accumulator of the complex sum on `d->device`.  Host-side argument
+ * errors return RAD_ERR_INVALID_ARG, device allocation failures RAD_ERR_OOM, other HIP
+ * failures RAD_ERR_DEVICE; *out is written only on success. */
 int rad_create_grid(rad_grid** out, const rad_grid_desc* d);
 
 /* Release a grid.  Waits for the grid's device to finish outstanding work first.
@@ -135,17 +140,23 @@ int rad_push_steps(rad_grid* g, double t0, int32_t n_steps, int64_t n_particles,
                    const rad_particles* p, void* stream);
 
 /* Read d^2I/(dOmega domega) [J s/sr] into I_host (HOST, n_dir x n_omega doubles,
- * row-major by direction).  Synchronises `stream`.  Non-destructive: accumulation may
- * continue afterwards.  Returns RAD_ERR_BAD_DATA (and writes nothing) if the flag is set. */
+ * row-major by direction): the squared modulus of the accumulated complex sum of Eq. 13
+ * (Sec. 3.3) times its prefactor, read as C = (q_e dt)^2 / (16 pi^3 eps0 c) -- the
+ * rectangle-rule dt of the time integral inside the square, which is what makes Eq. 13
+ * consistent in units with Eq. 1 (the printed prefactor has dt and q_e outside it).
+ * Synchronises `stream`.  Non-destructive: accumulation may continue afterwards.  Returns
+ * RAD_ERR_BAD_DATA (and writes nothing) if the flag is set. */
 int rad_spectrum(rad_grid* g, double* I_host, void* stream);
 
-/* Same as rad_spectrum into a DEVICE buffer of n_dir x n_omega doubles, without
- * synchronising; the data-error flag is not checked. */
+/* Same as rad_spectrum (Eq. 13's C |.|^2) into a DEVICE buffer of n_dir x n_omega
+ * doubles, without synchronising; the data-error flag is not checked.  Later pushes and
+ * resets of the grid, on any stream, take effect only after this read-out. */
 int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream);
 
-/* Read the complex spectrum S(n, omega) (without the prefactor) into S_host (HOST,
- * n_dir x n_omega x 3 complex, interleaved re/im: index ((d*n_omega + k)*3 + c)*2).
- * Synchronises `stream`. */
+/* Read the complex spectrum S(n, omega) -- the vector sum inside |.|^2 of Eq. 13
+ * (Sec. 3.3), without the prefactor C -- into S_host (HOST, n_dir x n_omega x 3 complex,
+ * Cartesian components, interleaved re/im: index ((d*n_omega + k)*3 + c)*2).
+ * Synchronises `stream`.  Returns RAD_ERR_BAD_DATA (and writes nothing) if the flag is set. */
 int rad_spectrum_complex(rad_grid* g, double* S_host, void* stream);
 
 /* Number of doubles in the opaque accumulator state of this grid. */
@@ -272,6 +283,8 @@ typedef struct rad_chunk_stats {
     double t_submit, t_admit, t_launch, t_complete;
     int32_t batch_size;
     int32_t status;          /* RAD_OK or the first error the server met */
+    int64_t batch_id;        /* 1, 2, ... in launch order: chunks with the same id shared
+                                one batched launch */
 } rad_chunk_stats;
 
 typedef struct rad_server_counters {
@@ -315,6 +328,12 @@ int rad_server_counters_read(rad_server* s, rad_server_counters* out);
  * applies).  Takes effect from the next batch. */
 int rad_server_set_tile(rad_server* s, const rad_tile* t);
 int rad_server_get_tile(rad_server* s, rad_tile* t);
+
+/* Kernel timing of the server's batched launches (as rad_batcher_profile_*: events on
+ * the server's compute stream around each launch; with graph replays, around the whole
+ * replay).  rad_server_profile_read waits for the recorded events. */
+int rad_server_profile_enable(rad_server* s, int enable);
+int rad_server_profile_read(rad_server* s, rad_profile_stats* out);
 
 /* Drain, stop the scheduler thread and free the server (not its grids). */
 int rad_server_destroy(rad_server* s);

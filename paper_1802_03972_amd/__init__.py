@@ -139,11 +139,6 @@ class Grid:
                                             _stream_handle(stream, self.device)))
         _in_use_on(keep, stream)
 
-    @staticmethod
-    def step_group() -> int:
-        """Steps one launch sums in registers per read-modify-write of the integrals."""
-        return int(_lib.lib().rad_tracked_step_group())
-
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         p, n, keep = make_particles(particles, device=self.device)
         if n_steps <= 0 or n % n_steps:
@@ -398,6 +393,14 @@ class Server:
 
     def drain(self) -> None:
         _lib.check(_lib.lib().rad_server_drain(self._h))
+
+    def profile(self, enable: bool = True) -> None:
+        _lib.check(_lib.lib().rad_server_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        st = _lib.ProfileStats()
+        _lib.check(_lib.lib().rad_server_profile_read(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _lib.ProfileStats._fields_}
 
     def counters(self) -> dict:
         c = _lib.ServerCounters()

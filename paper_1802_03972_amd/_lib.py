@@ -64,7 +64,8 @@ class ServerConfig(ctypes.Structure):
 
 class ChunkStats(ctypes.Structure):
     _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
-                ("t_complete", ctypes.c_double), ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("t_complete", ctypes.c_double), ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("batch_id", ctypes.c_int64)]
 
 
 class ServerCounters(ctypes.Structure):
@@ -116,6 +117,8 @@ SIGNATURES = {
     "rad_server_counters_read": (ctypes.c_int, [_vp, ctypes.POINTER(ServerCounters)]),
     "rad_server_set_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
     "rad_server_get_tile": (ctypes.c_int, [_vp, ctypes.POINTER(Tile)]),
+    "rad_server_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "rad_server_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ProfileStats)]),
     "rad_server_destroy": (ctypes.c_int, [_vp]),
     "rad_tracked_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(GridDesc), ctypes.c_int64]),
     "rad_tracked_destroy": (ctypes.c_int, [_vp]),

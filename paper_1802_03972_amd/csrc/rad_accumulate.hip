@@ -18,11 +18,11 @@
 //        shared by the workgroup's TO frequencies;
 //     3. per (particle, frequency) form-factor weight F = sqrt(N (1-g) + N^2 g) (Eq. 12),
 //        shared by the workgroup's TD directions;
-//     4. the hot loop: per particle, each lane seeds z = exp(i omega_first tau) from the
-//        FP64 phase (reduced to [0, 1) revolutions before leaving FP64), then walks its W
-//        frequencies with the three-term recurrence z_{k+1} = 2 cos(domega tau) z_k - z_{k-1}
-//        (uniform omega steps), scaling by F and accumulating.  8 FP32 VALU operations per
-//        update: 2 (scale) + 4 (two complex multiply-adds) + 2 (recurrence).
+//     4. the hot loop: per particle, each lane seeds z = exp(i omega tau) at the middle
+//        frequency of its block from the FP64 phase (reduced to [0, 1) revolutions before
+//        leaving FP64), then walks its W frequencies forward and backward by complex
+//        products with w (uniform omega steps), scaling by F and accumulating.  10 FP32 VALU
+//        operations per update: 2 (scale) + 4 (two complex multiply-adds) + 4 (rotation).
 // * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
 //   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
 
@@ -40,6 +40,7 @@
 namespace rad {
 
 namespace {
+
 
 // Accumulate chunks [c_begin, c_end) of `j` into the tile (td, tw) and write the FP32
 // partial tile: element (omega o, direction d) of the tile goes to out[o * row + d] (as
@@ -81,6 +82,13 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     // piecewise-uniform list: this lane's block spacing (the lane's frequencies are one block)
     double bstep = 0.0;
     if constexpr (BSTEP) bstep = j.bstep[(o_first < j.n_omega ? o_first : j.n_omega - 1) / kBlockW];
+    // The lane's W frequencies are walked from one FP64-seeded frequency by complex
+    // products with the rotation w = exp(i domega tau).  The seed is the middle of the block
+    // (index KS = W/2, on the block's own progression), and the walk goes forward and
+    // backward from it, so no frequency is more than W/2 products from its seed (the
+    // rounding of w accumulates once per product).
+    constexpr int KS = DIRECT ? 0 : W / 2;
+    const double om_seed = om_first + (double)KS * (BSTEP ? bstep : j.domega);
     // explicit frequencies (direct phase) and direction-dependent shape factors of this lane
     double om[DIRECT ? W : 1];
     float gl[SHAPE3 ? W : 1];
@@ -144,13 +152,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             float2 g = make_float2(0.f, 0.f);
             if (og < j.n_omega) g = j.gtab[og];
             float* dst = ff + o;
-            // the three-term recurrence carries x_k = sigma_k z_k (sigma = + + - - per 4
-            // frequencies); the weight carries the same sign so that F x_k = F_k z_k
-            const float sg = (!DIRECT && (o & 2)) ? -1.f : 1.f;
 #pragma unroll 8
             for (int m = 0; m < P; ++m, dst += TO) {
                 const float2 N = nw[m];
-                *dst = sg * __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
+                *dst = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
             }
         }
         __syncthreads();
@@ -162,10 +167,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             float zr = 1.f, zi = 0.f;
             if constexpr (!DIRECT) {
                 if constexpr (PREC == 0) {
-                    const double rv = frac_rev(om_first * ph);
-                    sincos_rev_fast(static_cast<float>(rv), zi, zr);
+                    sincos_rev_fast(static_cast<float>(frac_rev(om_seed * ph)), zi, zr);
                 } else {
-                    float rv = (float)om_first * (float)ph;
+                    float rv = (float)om_seed * (float)ph;
                     rv -= floorf(rv);
                     sincos_rev_fast(rv, zi, zr);
                 }
@@ -175,7 +179,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             if constexpr (BSTEP) {
                 // the block's own rotation exp(i bstep tau), from the FP64 phase
                 if constexpr (PREC == 0) {
-                    sincos_rev_fast(static_cast<float>(frac_rev(bstep * ph)), wi, wr);
+                    sincos_rev_f64(frac_rev(bstep * ph), wi, wr);
                 } else {
                     float rw = (float)bstep * (float)ph;
                     rw -= floorf(rw);
@@ -189,13 +193,12 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 Nm = Nv.x;
                 NN1 = Nv.y - Nv.x;   // N^2 - N
             }
-            // the lane's weights for frequencies 4q .. 4q+3 (signed as the recurrence needs)
+            // the lane's weights for frequencies 4q .. 4q+3
             auto weights = [&](int q, float (&Fv)[4]) {
                 if constexpr (SHAPE3) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {   // F^2 = N + (N^2 - N) g(n, omega) (Eq. 12)
-                        const float f = __builtin_amdgcn_sqrtf(fmaxf(fmaf(NN1, gl[4 * q + u], Nm), 0.f));
-                        Fv[u] = (!DIRECT && (u & 2)) ? -f : f;
+                        Fv[u] = __builtin_amdgcn_sqrtf(fmaxf(fmaf(NN1, gl[4 * q + u], Nm), 0.f));
                     }
                 } else {
                     const float4 F4 = fq[q];
@@ -231,39 +234,43 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     }
                 }
             } else {
-                // Uniform steps: the three-term recurrence z_{k+1} = 2 cos(theta) z_k - z_{k-1}
-                // (theta = domega tau), two multiply-adds per frequency instead of a complex
-                // product.  It runs on x_k = sigma_k z_k with sigma = (+, +, -, -) repeating,
-                // so that every step is a plain multiply-add into the older register,
-                // x_{k+1} = c_k x_k + x_{k-1}, c_k = 2 cos(theta) for even k and -2 cos(theta)
-                // for odd k; the weights carry sigma_k.  x_0 = z_0 comes from the FP64 phase,
-                // x_1 = z_0 w from one complex product.  Opaque negations (empty asm) keep every
-                // operation a VOP2 product or multiply-add without source modifiers.
+                // Uniform steps (or a block's own step): z_{k+1} = z_k w forward from the seed
+                // and z_{k-1} = z_k conj(w) backward from it -- complex products, two products
+                // and two multiply-adds per frequency.  Their error grows by about one
+                // rounding of w per product whatever theta = domega tau is (a three-term
+                // recurrence 2 cos(theta) z_k - z_{k-1} is cheaper but divides the rounding of
+                // 2 cos(theta) by sin(theta), which ruins terms whose step is near 0 or pi).
+                // The opaque negation keeps every operation a VOP2 product or multiply-add
+                // without source modifiers.
                 float nwi = -wi;
                 asm volatile("" : "+v"(nwi));
-                const float cp = wr + wr;
-                float cn = -cp;
-                asm volatile("" : "+v"(cn));
-                float pr = zr, pi = zi;                                         // x_{k-1}
-                float qr = fmaf(zr, wr, zi * nwi), qi = fmaf(zr, wi, zi * wr);  // x_k, k = 1
+                float fr = zr, fi = zi;
 #pragma unroll
-                for (int q = 0; q < W / 4; ++q) {
+                for (int q = KS / 4; q < W / 4; ++q) {
                     float Fv[4];
                     weights(q, Fv);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int k = 4 * q + u;
-                        if (k == 0) {
-                            add(0, Fv[0], pr, pi);
-                            continue;
-                        }
-                        add(k, Fv[u], qr, qi);
+                        add(k, Fv[u], fr, fi);
                         if (k + 1 < W) {
-                            const float ck = (k & 1) ? cn : cp;
-                            const float nr = fmaf(ck, qr, pr), ni = fmaf(ck, qi, pi);
-                            pr = qr; pi = qi;
-                            qr = nr; qi = ni;
+                            const float nr = fmaf(fr, wr, fi * nwi), ni = fmaf(fr, wi, fi * wr);
+                            fr = nr;
+                            fi = ni;
                         }
+                    }
+                }
+                float br = zr, bi = zi;
+#pragma unroll
+                for (int q = KS / 4 - 1; q >= 0; --q) {
+                    float Fv[4];
+                    weights(q, Fv);
+#pragma unroll
+                    for (int u = 3; u >= 0; --u) {
+                        const float nr = fmaf(br, wr, bi * wi), ni = fmaf(bi, wr, br * nwi);
+                        br = nr;
+                        bi = ni;
+                        add(4 * q + u, Fv[u], br, bi);
                     }
                 }
             }

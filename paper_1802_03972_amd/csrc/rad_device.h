@@ -33,6 +33,24 @@ __device__ __forceinline__ void sincos_rev_accurate(float r, float& s, float& c)
     sincospif(2.0f * r, &s, &c);
 }
 
+// exp(2 pi i r) for a phase r in revolutions held in FP64 (r in [0, 1]): sin/cos of the
+// FP32-rounded r, corrected to first order for that rounding (the FP32 argument alone is
+// off by up to 3e-8 revolutions, 1.9e-7 rad).  ACCURATE selects the library sin/cos
+// (about 4e-8 absolute error measured) over the hardware one (about 1.1e-7).
+template <bool ACCURATE = false>
+__device__ __forceinline__ void sincos_rev_f64(double r, float& s, float& c)
+{
+    const float rh = static_cast<float>(r);
+    float sh, ch;
+    if constexpr (ACCURATE) sincos_rev_accurate(rh, sh, ch);
+    else sincos_rev_fast(rh, sh, ch);
+    const float d = static_cast<float>(r - static_cast<double>(rh)) * 6.28318530717958648f;
+    s = fmaf(ch, d, sh);
+    c = fmaf(-sh, d, ch);
+}
+
+
+
 __device__ __forceinline__ void flag_error(int* err)
 {
     atomicOr(err, 1);
@@ -80,10 +98,9 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
         ph = tau * kInv2Pi;
         wr = 1.f;
         wi = 0.f;
-        if constexpr (WANT_W) {
-            const double rw = frac_rev(domega * ph);
-            sincos_rev_fast(static_cast<float>(rw), wi, wr);
-        }
+        // w is reused by every product of a lane's walk (its angle error grows once per
+        // product) and is shared by all the frequencies of a workgroup: accurate sin/cos
+        if constexpr (WANT_W) sincos_rev_f64<true>(frac_rev(domega * ph), wi, wr);
         bad = !(D > 0.0) || !(N >= 0.0) || !isfinite(N) || !isfinite(ph) || !isfinite(A1) ||
               !isfinite(A2);
     } else {

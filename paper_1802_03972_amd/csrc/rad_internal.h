@@ -101,6 +101,7 @@ void set_last_error(const char* msg);
 // Launchers (stream-ordered, return hipError_t).
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
                              int n_blocks, hipStream_t st);
+// count = 4 * grid points (FP32 values per split); part is 16-byte aligned.
 hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st);
 hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,
                                    float* seg_part, int dtype, int precision,

@@ -25,8 +25,8 @@ namespace {
 // frequency blocks), TD = NT / OB.  The steps of a push are taken S = OB at a
 // time: the S x TD (step, direction) geometries (FP64, as in the main path) are computed
 // once, one per thread, into LDS, then every thread walks its W frequencies for each of the
-// S steps with the main path's three-term recurrence (or, for explicit frequency lists, the
-// per-term FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W
+// S steps with the main path's complex-product walk from the block's middle frequency (or,
+// for explicit frequency lists, the per-term FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W
 // frequencies.  Up to kStepGroup steps of one push are summed in FP32 registers before one
 // read-modify-write of the FP64 integrals, so a multi-step push moves 64 B per particle and
 // grid point per group instead of per step (the main path likewise sums hundreds of
@@ -93,7 +93,8 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
     const bool live = d < a.n_dir && ob < n_blocks;
     const int o0 = (ob < n_blocks ? ob : n_blocks - 1) * W;
     const int kmax = a.n_omega - o0 < W ? a.n_omega - o0 : W;
-    const double om0 = a.omega[o0];
+    constexpr int KS = W / 2;                     // seeded frequency of the block
+    const double om_seed = a.omega[o0] + (double)KS * a.domega;
     double om[DIRECT ? W : 1];
     if constexpr (DIRECT) {
 #pragma unroll
@@ -147,27 +148,30 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
                         add(k, zr, zi);
                     }
                 } else {
-                    // the main path's three-term recurrence on x_k = sigma_k z_k, sigma =
-                    // (+, +, -, -) repeating; the sign is taken off when the sums are stored
+                    // the main path's walk: complex products with w forward and with conj(w)
+                    // backward from the seed at frequency KS
                     float zr, zi;
-                    sincos_rev_fast(static_cast<float>(frac_rev(om0 * ph)), zi, zr);
-                    float nwi = -gv.w;
+                    sincos_rev_fast(static_cast<float>(frac_rev(om_seed * ph)), zi, zr);
+                    const float wr = gv.z, wi = gv.w;
+                    float nwi = -wi;
                     asm volatile("" : "+v"(nwi));
-                    const float cp = gv.z + gv.z;
-                    float cn = -cp;
-                    asm volatile("" : "+v"(cn));
-                    float pr = zr, pi = zi;                                             // x_{k-1}
-                    float qr = fmaf(zr, gv.z, zi * nwi), qi = fmaf(zr, gv.w, zi * gv.z);  // x_k, k = 1
-                    add(0, pr, pi);
+                    float fr = zr, fi = zi;
 #pragma unroll
-                    for (int k = 1; k < W; ++k) {
-                        add(k, qr, qi);
+                    for (int k = KS; k < W; ++k) {
+                        add(k, fr, fi);
                         if (k + 1 < W) {
-                            const float ck = (k & 1) ? cn : cp;
-                            const float nr = fmaf(ck, qr, pr), ni = fmaf(ck, qi, pi);
-                            pr = qr; pi = qi;
-                            qr = nr; qi = ni;
+                            const float nr = fmaf(fr, wr, fi * nwi), ni = fmaf(fr, wi, fi * wr);
+                            fr = nr;
+                            fi = ni;
                         }
+                    }
+                    float br = zr, bi = zi;
+#pragma unroll
+                    for (int k = KS - 1; k >= 0; --k) {
+                        const float nr = fmaf(br, wr, bi * wi), ni = fmaf(bi, wr, br * nwi);
+                        br = nr;
+                        bi = ni;
+                        add(k, br, bi);
                     }
                 }
             }
@@ -189,11 +193,10 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
                 for (int u = 0; u < G; ++u) {
                     const int k = q + u;
                     if (k < kmax) {
-                        const double sg = (!DIRECT && (k & 2)) ? -1.0 : 1.0;
-                        t[u].x += sg * (double)acc[k].x;
-                        t[u].y += sg * (double)acc[k].y;
-                        t[u].z += sg * (double)acc[k].z;
-                        t[u].w += sg * (double)acc[k].w;
+                        t[u].x += (double)acc[k].x;
+                        t[u].y += (double)acc[k].y;
+                        t[u].z += (double)acc[k].z;
+                        t[u].w += (double)acc[k].w;
                         T[k * stride] = t[u];
                     }
                 }
@@ -224,15 +227,48 @@ __global__ void k_tracked_finalize(const double* __restrict__ T, const double* _
     I[(int64_t)d * n_omega + k] = C * (s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3);
 }
 
-// S[i] += sum over splits of part[s][i], in split order, in FP64.
-__global__ void k_fold(const float* __restrict__ part, double* __restrict__ S, int splits,
-                       int64_t count)
+// S[p] += sum over splits of part[s][p] for every grid point p (four components: S1r,
+// S1i, S2r, S2i), in split order, in FP64.  One thread per point reads 16 B per split with
+// kFoldUnroll loads in flight (the partials are read once: non-temporal loads), so few
+// waves keep HBM busy while the next push's accumulate holds the rest of the CUs.
+constexpr int kFoldUnroll = 16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_fold(const f32x4* __restrict__ part, double* __restrict__ S,
+                                              int splits, int64_t points)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += (double)part[(int64_t)k * count + i];
-    S[i] += s;
+    if (i >= points) return;
+    const f32x4* p = part + i;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
+    for (; k + kFoldUnroll <= splits; k += kFoldUnroll) {
+        f32x4 v[kFoldUnroll];
+#pragma unroll
+        for (int u = 0; u < kFoldUnroll; ++u) v[u] = __builtin_nontemporal_load(p + (int64_t)(k + u) * points);
+#pragma unroll
+        for (int u = 0; u < kFoldUnroll; ++u) {
+            a0 += (double)v[u].x;
+            a1 += (double)v[u].y;
+            a2 += (double)v[u].z;
+            a3 += (double)v[u].w;
+        }
+    }
+    for (; k < splits; ++k) {
+        const f32x4 v = __builtin_nontemporal_load(p + (int64_t)k * points);
+        a0 += (double)v.x;
+        a1 += (double)v.y;
+        a2 += (double)v.z;
+        a3 += (double)v.w;
+    }
+    double2* s2 = reinterpret_cast<double2*>(S) + 2 * i;
+    double2 lo = s2[0], hi = s2[1];
+    lo.x += a0;
+    lo.y += a1;
+    hi.x += a2;
+    hi.y += a3;
+    s2[0] = lo;
+    s2[1] = hi;
 }
 
 // Batched fold: for every (grid, tile) job and every in-grid point of the tile, add the
@@ -331,7 +367,10 @@ hipError_t launch_fold_batch(const int32_t* n_jobs_dev, const FoldJob* jobs, int
 
 hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fold, dim3(grid1d(count, 256)), dim3(256), 0, st, part, S, splits, count);
+    const int64_t points = count / 4;
+    if (points <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold, dim3(grid1d(points, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const f32x4*>(part), S, splits, points);
     return hipGetLastError();
 }
 

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -309,19 +311,13 @@ void fill_job(rad::Job& j, const rad_grid* g, const rad_particles* p, double t0,
     j.err = g->d_err;
 }
 
-// Accumulate particles [0, total) (step of element i is i / n_per_step, t = t0 + step*dt).
-int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const rad_particles* p,
-               hipStream_t st)
+// Cuts particles [0, total) into launches of at most target_splits particle splits of at
+// most kMaxPerWorkgroup particles each, and sets a's particle range, split count and
+// chunks per split for each launch before calling fn() (which returns a status code).
+template <typename Fn>
+int for_each_launch(AccArgs& a, int64_t total, int64_t target_splits, Fn fn)
 {
-    int rc = ensure_partials(g);
-    if (rc) return rc;
-    const LaunchShape ls = shape_of(g->tile, g->variant);
-    const int td = tiles_d(g), tw = tiles_w(g), nt = td * tw;
-    const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;
-    const int64_t target_splits = max_splits(g);   // <= part_splits (capacity may be larger)
     const int64_t per_launch_cap = target_splits * kMaxPerWorkgroup;
-    AccArgs a{};
-    fill_job(a.job, g, p, t0, n_per_step, g->tile);
     for (int64_t i0 = 0; i0 < total; i0 += per_launch_cap) {
         const int64_t i1 = std::min(total, i0 + per_launch_cap);
         const int64_t nchunks = (i1 - i0 + rad::kChunk - 1) / rad::kChunk;
@@ -332,6 +328,25 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
         a.job.i_end = i1;
         a.splits = (int32_t)splits;
         a.chunks_per_split = cps;
+        if (int rc = fn()) return rc;
+    }
+    return RAD_OK;
+}
+
+// Accumulate particles [0, total) (step of element i is i / n_per_step, t = t0 + step*dt).
+int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const rad_particles* p,
+               hipStream_t st)
+{
+    int rc = ensure_partials(g);
+    if (rc) return rc;
+    const LaunchShape ls = shape_of(g->tile, g->variant);
+    const int td = tiles_d(g), tw = tiles_w(g), nt = td * tw;
+    const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;
+    const int64_t target_splits = max_splits(g);   // <= part_splits (capacity may be larger)
+    AccArgs a{};
+    fill_job(a.job, g, p, t0, n_per_step, g->tile);
+    return for_each_launch(a, total, target_splits, [&]() -> int {
+        const int64_t i0 = a.job.i_begin, i1 = a.job.i_end, splits = a.splits;
         const int b = g->part_next;
         g->part_next ^= 1;
         a.part = g->d_part[b];
@@ -360,8 +375,8 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
         RAD_HIP(hipEventRecord(g->ev_fold_done[b], g->fold_stream));
         g->fold_recorded[b] = true;
         g->last_fold = b;
-    }
-    return RAD_OK;
+        return RAD_OK;
+    });
 }
 
 // Make `st` wait for every fold already enqueued (the fold stream is in order, so the
@@ -648,10 +663,14 @@ int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream)
 {
     if (!g || !I_dev) return fail(RAD_ERR_INVALID_ARG, "grid and output must be non-NULL");
     DeviceGuard dg(g->device);
-    if (int rc0 = after_folds(g, (hipStream_t)stream)) return rc0;
-    hipError_t e = rad::launch_finalize(g->d_S, I_dev, g->n_dir, g->n_omega, g->C, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc0 = after_folds(g, st)) return rc0;
+    hipError_t e = rad::launch_finalize(g->d_S, I_dev, g->n_dir, g->n_omega, g->C, st);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
-    return RAD_OK;
+    // The read-out does not synchronise: later folds (on the fold stream) and resets (on
+    // any stream, which wait for the last fold) must not write S before it has been read.
+    RAD_HIP(hipEventRecord(g->ev_write, st));
+    return chain_fold_stream(g, g->ev_write);
 }
 
 int rad_spectrum(rad_grid* g, double* I_host, void* stream)

@@ -217,12 +217,13 @@ struct rad_server {
         if (rc != RAD_OK) set_error(rc, std::string("batched launch: ") + rad_last_error());
         if (!b.done || hipEventRecord(b.done, compute_stream) != hipSuccess)
             set_error(RAD_ERR_DEVICE, "cannot record batch event");
+        counters.batches += 1;
         for (uint64_t tk : ready) {
             Chunk& c = chunks[tk];
             c.st.t_launch = tl;
             c.st.batch_size = (int32_t)ready.size();
+            c.st.batch_id = counters.batches;
         }
-        counters.batches += 1;
         counters.chunks_launched += (int64_t)ready.size();
         inflight.push_back(std::move(b));
         return true;
@@ -416,6 +417,20 @@ int rad_server_get_tile(rad_server* s, rad_tile* t)
     if (!s || !t) return srv_fail(RAD_ERR_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
     return rad_batcher_get_tile(s->batcher, t);
+}
+
+int rad_server_profile_enable(rad_server* s, int enable)
+{
+    if (!s) return srv_fail(RAD_ERR_INVALID_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);   // the scheduler pushes batches under this lock
+    return rad_batcher_profile_enable(s->batcher, enable);
+}
+
+int rad_server_profile_read(rad_server* s, rad_profile_stats* out)
+{
+    if (!s || !out) return srv_fail(RAD_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return rad_batcher_profile_read(s->batcher, out);
 }
 
 int rad_server_destroy(rad_server* s)

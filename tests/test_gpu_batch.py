@@ -1,15 +1,16 @@
 """Batched persistent launch over several grids (uneven bunches), through the C ABI.
 
-Each grid's spectrum from one batched push must equal the oracle (1e-4 of the peak), the
-per-grid push of the same particles (FP32 rounding only), and the same bunch pushed alone
-(alone vs in the mix).  Repeating the same mix is bitwise reproducible.
+Each grid's spectrum from one batched push must equal the oracle (1e-4, globally and
+frequency by frequency), the per-grid push of the same particles (FP32 rounding only), and
+the same bunch pushed alone (alone vs in the mix).  Repeating the same mix is bitwise
+reproducible.
 """
 import numpy as np
 import pytest
 
 import oracle
 from workloads import SINGLE, batched_uneven, flatten
-from tests.helpers import e_inf, to_device
+from tests.helpers import assert_close, assert_parity, in_block_sample, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -50,12 +51,12 @@ def test_batch_matches_oracle_and_single_pushes(rad):
         if w.n_particles <= 3000:
             Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape,
                                    w.shape_len, w.dt)
-            err = e_inf(I, Iref)
-            print(f"batch n={w.n_particles}: e_inf vs oracle {err:.3e}")
-            assert err <= TOL
+            assert_parity(I, Iref, f"batch n={w.n_particles} vs oracle")
         g1 = grid_for(rad, w)
         g1.push_steps(w.t0, w.n_steps, d)
-        assert e_inf(I, g1.spectrum()) <= 1e-6
+        # the batch's tuned tile walks 16 frequencies per lane, the grid's 32: per-term
+        # recurrence rounding differs, so the per-frequency bound is the parity tolerance
+        assert_close(I, g1.spectrum(), f"batch n={w.n_particles} vs per-grid push", tol_freq=TOL)
 
 
 def test_alone_vs_in_the_mix(rad):
@@ -70,7 +71,7 @@ def test_alone_vs_in_the_mix(rad):
         alone = grid_for(rad, w)
         b.push([(alone, w.t0, w.n_steps, d)])
         Im = mixed[k].spectrum()
-        assert e_inf(Im, alone.spectrum()) <= 1e-6
+        assert_close(Im, alone.spectrum(), f"bunch {k}: in the mix vs alone")
         assert np.array_equal(Im, again[k].spectrum())
 
 
@@ -84,7 +85,7 @@ def test_several_items_on_one_grid(rad):
     first = {k: v[:2 * n] for k, v in d.items()}
     second = {k: v[2 * n:] for k, v in d.items()}
     rad.Batcher().push([(g_split, w.t0, 2, first), (g_split, w.t0 + 2 * w.dt, 2, second)])
-    assert e_inf(g_split.spectrum(), g_all.spectrum()) <= 1e-6
+    assert_close(g_split.spectrum(), g_all.spectrum(), "two items on one grid", tol_freq=TOL)
 
 
 @pytest.mark.parametrize("grid_tiles,batch_tile", [
@@ -112,10 +113,12 @@ def test_batch_mixes_grid_shapes_and_tiles(rad, grid_tiles, batch_tile):
     b.push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
     for g, w, st, d in zip(grids, ws, sts, devs):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
-        assert e_inf(g.spectrum(), Iref) <= TOL
+        assert_parity(g.spectrum(), Iref, f"mixed shapes/tiles {batch_tile}")
         single = grid_for(rad, w)
         single.push_steps(w.t0, w.n_steps, d)
-        assert e_inf(g.spectrum(), single.spectrum()) <= 1e-6
+        # the batch may walk 32 frequencies per lane where the grid walks 16: per-term
+        # recurrence rounding differs, so the per-frequency bound is the parity tolerance
+        assert_close(g.spectrum(), single.spectrum(), "batched vs single push", tol_freq=TOL)
 
 
 def test_batch_rejects_mixed_precision(rad):
@@ -140,15 +143,13 @@ def test_batched_uneven_full_counts_one_step(rad):
     devs = [to_device(st, w.in_dtype) for w, st in zip(ws, sts)]
     rad.Batcher(max_items=16).push([(g, w.t0, 1, d) for g, w, d in zip(grids, ws, devs)])
     order = np.argsort(mb.counts)
-    sel = np.arange(0, 256, 16)
-    for k in (order[0], order[len(order) // 2]):
+    sel = in_block_sample(256)
+    for k in (order[0], order[len(order) // 2], order[-1]):
         w = ws[k]
         I = grids[k].spectrum()[:, sel]
         Iref = oracle.spectrum(flatten(sts[k], w.times()), w.directions(), w.omegas()[sel], w.shape,
                                w.shape_len, w.dt)
-        err = e_inf(I, Iref)
-        print(f"batched_uneven bunch {k} (n={w.n_particles}): e_inf {err:.3e}")
-        assert err <= TOL
+        assert_parity(I, Iref, f"batched_uneven bunch {k} (n={w.n_particles})", ks=sel)
 
 
 def test_graph_replays_match_direct_launches(rad):
@@ -195,7 +196,7 @@ def test_batch_then_single_pushes_on_other_streams(rad):
         r.push_steps(w.t0, w.n_steps, d)
         r.push_steps(w.t0 + 5 * w.dt, w.n_steps, d)
     for a, r in zip(I, ref):
-        assert e_inf(a, r.spectrum()) <= 1e-6
+        assert_close(a, r.spectrum(), "batched push, then pushes and read-out on other streams", tol_freq=TOL)
 
 
 def test_checkpoint_after_batched_push(rad):

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 from workloads import TINY, FIELDS, flatten
+from tests.helpers import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -32,9 +33,7 @@ def test_c_program_matches_oracle(tmp_path, shape, shape_id):
     I = np.fromfile(out, np.float64).reshape(w.n_dir, w.n_omega)
     times = w.t0 + np.arange(w.n_steps) * w.dt
     Iref = oracle.spectrum(flatten(st, times), dirs, w.omegas(), shape, w.shape_len, w.dt)
-    err = float(np.max(np.abs(I - Iref)) / np.max(Iref))
-    print(f"C program ({shape}): e_inf {err:.3e}")
-    assert err <= 1e-4
+    assert_parity(I, Iref, f"C program ({shape})")
 
 
 def test_c_program_reports_errors(tmp_path):

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from workloads import SINGLE, flatten, direction_grid, block_log_omegas
-from tests.helpers import e_inf, to_device
+from tests.helpers import assert_parity, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +69,5 @@ def test_random_configuration(rad, k):
     b.push([(gb, w.t0, w.n_steps, dev)])
     desc = (f"case {k}: {len(dirs)} dirs x {len(omegas)} omega, {w.n_particles} x {w.n_steps} {w.in_dtype}, "
             f"{w.shape}, variant {g.variant}, tile {tile}, batch {btile}")
-    e1, e2 = e_inf(g.spectrum(), Iref), e_inf(gb.spectrum(), Iref)
-    print(f"{desc}: e_inf {e1:.2e} / batched {e2:.2e}", flush=True)
-    assert e1 <= TOL and e2 <= TOL, desc
+    assert_parity(g.spectrum(), Iref, desc)
+    assert_parity(gb.spectrum(), Iref, desc + " (batched)")

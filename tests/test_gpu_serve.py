@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from workloads import SINGLE, flatten, FIELDS
-from tests.helpers import e_inf, to_device
+from tests.helpers import assert_close, assert_parity, in_block_sample, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -65,13 +65,11 @@ def test_server_matches_direct_pushes_and_oracle(rad):
         I = g.spectrum()
         direct = grid_for(rad, w)
         direct.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
-        assert e_inf(I, direct.spectrum()) <= 1e-6
+        assert_close(I, direct.spectrum(), f"served bunch n={w.n_particles} vs direct push")
         if w.n_particles <= 1200:
             Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape,
                                    w.shape_len, w.dt)
-            err = e_inf(I, Iref)
-            print(f"served bunch n={w.n_particles}: e_inf vs oracle {err:.3e}")
-            assert err <= TOL
+            assert_parity(I, Iref, f"served bunch n={w.n_particles} vs oracle")
     for s in stats:
         assert s["status"] == 0
         assert s["t_submit"] <= s["t_admit"] <= s["t_launch"] <= s["t_complete"]
@@ -88,7 +86,7 @@ def test_tight_budget_defers_but_never_drops(rad):
     ref = [grid_for(rad, w) for w, _ in bs]
     for g, r, (w, st) in zip(grids, ref, bs):
         r.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
-        assert e_inf(g.spectrum(), r.spectrum()) <= 1e-6
+        assert_close(g.spectrum(), r.spectrum(), "tight budget vs direct push")
 
 
 def test_oversized_chunk_rejected(rad):
@@ -119,4 +117,63 @@ def test_server_launch_shape(rad):
     for g, (w, st) in zip(grids, bs):
         direct = grid_for(rad, w)
         direct.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
-        assert e_inf(g.spectrum(), direct.spectrum()) <= 1e-6
+        assert_close(g.spectrum(), direct.spectrum(), "explicit server launch shape vs direct push")
+
+
+def test_continuous_batching(rad):
+    """Requests that arrive while others are on the GPU are admitted and launched without
+    waiting for the earlier work to drain.  A first set of large chunks (two bunches) is
+    submitted; once the server reports a batch in flight, a second set from two other
+    bunches arrives.  Some second-set chunk must be admitted before some first-set chunk
+    has completed, some batched launch must mix bunches, and every bunch's served spectrum
+    must equal the same bunch pushed alone (FP32 rounding) and the oracle (parity gate)."""
+    import time
+    from collections import defaultdict
+    big = make_bunches([90000, 70000], steps=10, n_omega=512)
+    small = [(w, w.steps()) for w in (SINGLE.scaled(n_particles=n, n_steps=10, nx_dir=4, ny_dir=8, n_omega=512,
+                                                   gamma=("uniform", 20.0, 500.0), seed=350 + i)
+                                      for i, n in enumerate((3000, 7000)))]
+    bs = big + small
+    grids = [grid_for(rad, w) for w, _ in bs]
+    srv = rad.Server(hbm_budget=512 << 20, max_batch=4, max_inflight=2)
+    tickets = []
+    for j in range(10):
+        for b in (0, 1):
+            w, st = bs[b]
+            tickets.append((srv.submit(grids[b], float(w.times()[j]), host_chunk(st, j)), b, 0))
+    t_end = time.perf_counter() + 60
+    while srv.counters()["inflight_batches"] < 1:
+        assert time.perf_counter() < t_end, "no batch went in flight"
+        time.sleep(1e-4)
+    seen_inflight = srv.counters()
+    for j in range(10):
+        for b in (2, 3):
+            w, st = bs[b]
+            tickets.append((srv.submit(grids[b], float(w.times()[j]), host_chunk(st, j)), b, 1))
+    srv.drain()
+    stats = [(srv.wait(tk), b, s) for tk, b, s in tickets]
+    srv.close()
+    print("counters when the second set arrived:", seen_inflight)
+    first = [st for st, _, s in stats if s == 0]
+    second = [st for st, _, s in stats if s == 1]
+    assert all(st["status"] == 0 for st, _, _ in stats)
+    last_first_done = max(st["t_complete"] for st in first)
+    early = [st for st in second if st["t_admit"] < last_first_done]
+    print(f"second-set chunks admitted before the first set completed: {len(early)} of {len(second)}")
+    assert early
+    members = defaultdict(set)
+    for st, b, _ in stats:
+        members[st["batch_id"]].add(b)
+    mixed = [k for k, v in members.items() if len(v) > 1]
+    print(f"{len(members)} batched launches, {len(mixed)} of them mix bunches")
+    assert mixed
+    ds = np.arange(0, 32, 4)
+    ks = in_block_sample(512, 32)
+    for g, (w, st) in zip(grids, bs):
+        I = g.spectrum()
+        alone = grid_for(rad, w)
+        alone.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
+        assert_close(I, alone.spectrum(), f"bunch n={w.n_particles}: served in the mix vs alone")
+        Iref = oracle.spectrum(flatten(st, w.times()), w.directions()[ds], w.omegas()[ks], w.shape,
+                               w.shape_len, w.dt)
+        assert_parity(I[np.ix_(ds, ks)], Iref, f"served bunch n={w.n_particles} vs oracle", ks=ks)

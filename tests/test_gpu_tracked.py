@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from workloads import SINGLE, flatten
-from tests.helpers import e_inf, to_device, step_slice
+from tests.helpers import assert_close, assert_parity, to_device, step_slice
 
 pytestmark = pytest.mark.gpu
 
@@ -45,9 +45,10 @@ def test_tracked_equals_in_situ_and_oracle(rad):
     g = rad.Grid(w.directions(), w.omega0, w.domega, w.n_omega, shape=w.shape, shape_len=w.shape_len, dt=w.dt)
     g.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
-    e_grid, e_or = e_inf(I, g.spectrum()), e_inf(I, Iref)
-    print(f"tracked vs in-situ {e_grid:.3e}, vs oracle {e_or:.3e}")
-    assert e_grid <= 1e-5 and e_or <= TOL
+    # 8 frequencies per thread in the tracked kernel, 16 per lane in the in-situ one: the
+    # recurrences are seeded at different frequencies
+    assert_close(I, g.spectrum(), "tracked vs in-situ", tol_inf=1e-5, tol_freq=TOL)
+    assert_parity(I, Iref, "tracked vs oracle")
 
 
 @pytest.mark.parametrize("shape", ["point", "tsc", "gauss", "qsc3d"])
@@ -58,9 +59,7 @@ def test_shape_chosen_after_the_run(rad, shape):
     tr = run_tracked(rad, w, st, dtype="f64")
     I = tr.spectrum(st["w"][0], shape, w.shape_len)
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), shape, w.shape_len, w.dt)
-    err = e_inf(I, Iref)
-    print(f"post-hoc shape {shape}: e_inf {err:.3e}")
-    assert err <= TOL
+    assert_parity(I, Iref, f"post-hoc shape {shape}")
 
 
 def test_weights_chosen_after_the_run(rad):
@@ -72,7 +71,7 @@ def test_weights_chosen_after_the_run(rad):
     I = tr.spectrum(wts, w.shape, w.shape_len)
     Iref = oracle.spectrum(flatten(with_weights(st, wts), w.times()), w.directions(), w.omegas(), w.shape,
                            w.shape_len, w.dt)
-    assert e_inf(I, Iref) <= TOL
+    assert_parity(I, Iref, "weights chosen after the run")
 
 
 def test_log_spaced_frequencies(rad):
@@ -82,8 +81,7 @@ def test_log_spaced_frequencies(rad):
     tr = run_tracked(rad, w, st, omegas=om)
     I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
-    col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
-    assert e_inf(I, Iref) <= TOL and col.max() <= TOL
+    assert_parity(I, Iref, "tracked, log-spaced frequencies")
 
 
 def test_reset_and_repeat_is_bitwise(rad):
@@ -133,8 +131,8 @@ def test_multi_step_push(rad, n_steps):
     I1 = one.spectrum(st["w"][0], w.shape, w.shape_len)
     I2 = many.spectrum(st["w"][0], w.shape, w.shape_len)
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
-    assert e_inf(I2, I1) <= 1e-6
-    assert e_inf(I2, Iref) <= TOL
+    assert_close(I2, I1, f"{n_steps}-step push vs per-step pushes")
+    assert_parity(I2, Iref, f"{n_steps}-step push vs oracle")
 
 
 @pytest.mark.parametrize("per_step", [False, True])
@@ -160,7 +158,5 @@ def test_tracked_tiling(rad, n_dir_xy, n_omega, omega_list, per_step):
     I = tr.spectrum(st["w"][0], w.shape, w.shape_len)
     omegas = om if omega_list else w.omegas()
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), omegas, w.shape, w.shape_len, w.dt)
-    err = e_inf(I, Iref)
-    print(f"tracked tiling {nx}x{ny} x {n_omega}: e_inf {err:.3e}")
     assert I.shape == (nx * ny, n_omega)
-    assert err <= TOL
+    assert_parity(I, Iref, f"tracked tiling {nx}x{ny} x {n_omega}, per_step={per_step}")

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from workloads import SINGLE, TINY, flatten, direction_grid, block_log_omegas
-from tests.helpers import e_inf, to_device
+from tests.helpers import assert_close, assert_complex_parity, assert_parity, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +30,7 @@ def test_log_spaced_frequencies_match_oracle(rad):
         g.push_steps(w.t0, w.n_steps, to_device(st, dtype))
         I = g.spectrum()
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
-        err = e_inf(I, Iref)
-        col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
-        print(f"log-spaced omega ({dtype}): e_inf {err:.3e}, per-frequency max {col.max():.3e}")
-        assert err <= TOL and col.max() <= TOL
+        assert_parity(I, Iref, f"log-spaced omega ({dtype})")
 
 
 def test_explicit_uniform_list_equals_recurrence(rad):
@@ -46,7 +43,8 @@ def test_explicit_uniform_list_equals_recurrence(rad):
     g2 = rad.Grid(w.directions(), 0.0, 0.0, 0, shape=w.shape, shape_len=w.shape_len, dt=w.dt, omegas=w.omegas())
     g1.push_steps(w.t0, 2, dev)
     g2.push_steps(w.t0, 2, dev)
-    assert e_inf(g2.spectrum(), g1.spectrum()) <= 2e-6
+    assert_close(g2.spectrum(), g1.spectrum(), "uniform list (per-term phase) vs recurrence", tol_inf=2e-6,
+                 tol_freq=TOL)
 
 
 @pytest.mark.parametrize("shape", ["cic3d", "tsc3d", "qsc3d"])
@@ -60,12 +58,9 @@ def test_cubic_cell_shapes_match_oracle(rad, shape):
     I = g.spectrum()
     Iref = oracle.spectrum(flatten(st, w.times()), dirs, w.omegas(), shape, w.shape_len, w.dt)
     I1d = oracle.spectrum(flatten(st, w.times()), dirs, w.omegas(), shape[:-2], w.shape_len, w.dt)
-    err = e_inf(I, Iref)
-    col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
+    assert_parity(I, Iref, shape)
     col1d = np.max(np.abs(I1d - Iref), axis=0) / np.max(Iref, axis=0)
-    print(f"{shape}: e_inf {err:.3e}, per-frequency {col.max():.3e}; 1-D shape instead differs per frequency "
-          f"by up to {col1d.max():.3e}")
-    assert err <= TOL and col.max() <= TOL
+    print(f"{shape}: the 1-D shape instead differs per frequency by up to {col1d.max():.3e}")
     assert col1d.max() > 100 * TOL      # the direction dependence is visible on this grid
 
 
@@ -78,7 +73,7 @@ def test_cubic_cell_along_axis_equals_1d_shape(rad):
     g1 = rad.Grid(dirs, w.omega0, w.domega, w.n_omega, shape="cic", shape_len=1e-7, dt=w.dt)
     g3.push_steps(w.t0, w.n_steps, dev)
     g1.push_steps(w.t0, w.n_steps, dev)
-    assert e_inf(g3.spectrum(), g1.spectrum()) <= 1e-6
+    assert_close(g3.spectrum(), g1.spectrum(), "cubic cell along the axis vs 1-D shape")
 
 
 def test_batch_of_frequency_list_grids(rad):
@@ -91,7 +86,7 @@ def test_batch_of_frequency_list_grids(rad):
     rad.Batcher().push([(g, w.t0, w.n_steps, d) for g, w, d in zip(grids, ws, devs)])
     for g, w, st in zip(grids, ws, sts):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
-        assert e_inf(g.spectrum(), Iref) <= TOL
+        assert_parity(g.spectrum(), Iref, "batch of log-list grids")
     uni = SINGLE.scaled(n_particles=100, n_steps=1, nx_dir=4, ny_dir=4, seed=40)
     gu = rad.Grid(uni.directions(), uni.omega0, uni.domega, 64, shape=uni.shape, shape_len=uni.shape_len, dt=uni.dt)
     with pytest.raises(rad.RadError):
@@ -134,10 +129,7 @@ def test_piecewise_uniform_list_matches_oracle(rad, shape, n_omega, dtype):
     g.push_steps(w.t0, w.n_steps, to_device(st, dtype))
     I = g.spectrum()
     Iref = oracle.spectrum(flatten(st, w.times()), dirs, om, shape, w.shape_len, w.dt)
-    err = e_inf(I, Iref)
-    col = np.max(np.abs(I - Iref), axis=0) / np.max(Iref, axis=0)
-    print(f"block-stepped list ({shape}, {n_omega}, {dtype}): e_inf {err:.3e}, per-frequency {col.max():.3e}")
-    assert err <= TOL and col.max() <= TOL
+    assert_parity(I, Iref, f"block-stepped list ({shape}, {n_omega}, {dtype})", ks=np.arange(n_omega))
 
 
 def test_piecewise_uniform_list_batched(rad):
@@ -159,10 +151,10 @@ def test_piecewise_uniform_list_batched(rad):
     assert gb.graph_stats()["launches"] >= 2
     for g, w, st, d in zip(grids, ws, sts, devs):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), om, w.shape, w.shape_len, w.dt)
-        assert e_inf(g.spectrum(), Iref) <= TOL
+        assert_parity(g.spectrum(), Iref, "batched block-stepped list")
         single = rad.Grid(w.directions(), 0.0, 0.0, 0, shape=w.shape, shape_len=w.shape_len, dt=w.dt, omegas=om)
         single.push_steps(w.t0, w.n_steps, d)
-        assert e_inf(g.spectrum(), single.spectrum()) <= 1e-6
+        assert_close(g.spectrum(), single.spectrum(), "batched vs single (block-stepped list)")
 
 
 def test_complex_spectrum_of_variant_grid(rad):
@@ -177,6 +169,4 @@ def test_complex_spectrum_of_variant_grid(rad):
     g.push_steps(w.t0, w.n_steps, to_device(st, "f64"))
     S = g.spectrum_complex()
     Sref = oracle.spectrum_complex(flatten(st, w.times()), dirs, om, "tsc3d", w.shape_len)
-    err = float(np.max(np.abs(S - Sref)) / np.max(np.abs(Sref)))
-    print(f"complex spectrum (variant 3): {err:.3e}")
-    assert err <= 1e-4
+    assert_complex_parity(S, Sref, "complex spectrum (variant 3)")

@@ -111,11 +111,22 @@ class Workload:
         return draw_bunch(rng, self.n_particles, self.gamma, self.weight,
                           x0_max=self.x0_max, omega_beta=self.omega_beta)
 
-    def steps(self, j0: int = 0, j1: int | None = None, bunch: Bunch | None = None) -> dict:
+    def steps(self, j0: int = 0, j1: int | None = None, bunch: Bunch | None = None,
+              workers: int = 1) -> dict:
         """Particle state for steps [j0, j1), arrays (steps, n), already rounded to the
-        ingest dtype (float32 configs) and returned as float64 views of those values."""
+        ingest dtype (float32 configs) and returned as float64 views of those values.
+        workers > 1 evaluates groups of steps on a thread pool (every step is a pure
+        function of its time, so the arrays do not depend on the worker count)."""
         b = self.bunch() if bunch is None else bunch
-        st = stack_steps(b, self.times(j0, j1))
+        times = self.times(j0, j1)
+        if workers > 1 and len(times) > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            parts = np.array_split(times, min(len(times), 4 * workers))
+            with ThreadPoolExecutor(workers) as ex:
+                pieces = list(ex.map(lambda ts: stack_steps(b, ts), parts))
+            st = {k: np.concatenate([p[k] for p in pieces]) for k in pieces[0]}
+        else:
+            st = stack_steps(b, times)
         if self.in_dtype == "f32":
             st = {k: v.astype(np.float32).astype(np.float64) for k, v in st.items()}
         return st
@@ -174,8 +185,42 @@ def serving_bunches(seed: int = 0, n_bunches: int = 8) -> MultiBunch:
     return MultiBunch("serving", counts, base, _spawn_seeds(seed + 1, n_bunches))
 
 
+def host_workers() -> int:
+    """Threads for input generation: the host cores this process may use, at most 16."""
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def poisson_trace(rate: float, n_chunks: int, n_bunches: int, seed: int = 0):
     """Arrival times [s] (Poisson process at `rate` per second) and the bunch of each chunk."""
     rng = np.random.default_rng(seed + 2)
     gaps = rng.exponential(1.0 / rate, n_chunks)
     return np.cumsum(gaps), rng.integers(0, n_bunches, n_chunks)
+
+
+@dataclass(frozen=True)
+class Fig3Analogue:
+    """Inputs of the synthetic analogue of the paper's Fig. 3 (Sec. 4): ONE macro-particle
+    of `electrons` electrons on a betatron trajectory (gamma 100, 2000 steps of 0.05 fs),
+    observed on axis and 10 mrad off axis over log-spaced frequencies 1e13 .. 1e19 rad/s,
+    with the Gaussian macro-particle shape `sigma`."""
+    electrons: float = 1e5
+    sigma: float = 0.1e-6
+    workload: Workload = TINY.scaled(n_particles=1, n_steps=2000, gamma=("const", 100.0), seed=5)
+
+    def directions(self) -> np.ndarray:
+        return np.array([[0.0, 0.0, 1.0], [0.01, 0.0, np.sqrt(1 - 1e-4)]])
+
+    def omegas(self) -> np.ndarray:
+        return np.geomspace(1e13, 1e19, 241)
+
+    def trajectory(self, weight: float) -> dict:
+        """(steps, 1) arrays of the one macro-particle with weighting `weight`."""
+        st = self.workload.steps()
+        out = dict(st)
+        out["w"] = np.full_like(st["w"], float(weight))
+        return out
