@@ -139,6 +139,27 @@ int rad_push_step(rad_grid* g, double t, int64_t n_particles, const rad_particle
 int rad_push_steps(rad_grid* g, double t0, int32_t n_steps, int64_t n_particles,
                    const rad_particles* p, void* stream);
 
+/* ---- push without device allocation -------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, ownership, ordering and
+ * result as rad_push_step, but the call allocates nothing (no hipMalloc or hipFree, no
+ * events or streams): the accumulate kernel's FP32 partial sums go to a fixed device
+ * array inside the library, RAD_NOALLOC_SCRATCH_BYTES on each GPU (reserved when the
+ * library's code is loaded on that GPU, held until the process ends), and the fold into
+ * the grid's accumulator runs on `stream` right after the accumulate.  The grid itself
+ * comes from rad_create_grid as usual.
+ * Limits: a grid needs 16 * n_dir * n_omega bytes of scratch per particle split; grids of
+ * more than RAD_NOALLOC_SCRATCH_BYTES / 16 points are rejected with RAD_ERR_INVALID_ARG,
+ * and a push uses at most RAD_NOALLOC_SCRATCH_BYTES / (16 * n_dir * n_omega) splits at a
+ * time (more launches for long pushes; the result then differs from rad_push_step's only
+ * by FP32 rounding of the partial sums).  Kernel timing (rad_profile_*) does not cover it.
+ * All calls on one GPU share the scratch and leave their partial sums in it: calls that
+ * can overlap on one GPU (issued on different streams with no ordering between them)
+ * race and give wrong results; order them on one stream. */
+#define RAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_particles* p,
+                          void* stream);
+
 /* Read d^2I/(dOmega domega) [J s/sr] into I_host (HOST, n_dir x n_omega doubles,
  * row-major by direction): the squared modulus of the accumulated complex sum of Eq. 13
  * (Sec. 3.3) times its prefactor, read as C = (q_e dt)^2 / (16 pi^3 eps0 c) -- the

@@ -139,6 +139,14 @@ class Grid:
                                             _stream_handle(stream, self.device)))
         _in_use_on(keep, stream)
 
+    def push_step_noalloc(self, t: float, particles: dict, stream=None) -> None:
+        """rad_push_step_noalloc: the same push without any device allocation (partial sums
+        in the library's fixed per-GPU scratch; calls on one GPU must not overlap)."""
+        p, n, keep = make_particles(particles, device=self.device)
+        _lib.check(_lib.lib().rad_push_step_noalloc(self._h, float(t), n, ctypes.byref(p),
+                                                    _stream_handle(stream, self.device)))
+        _in_use_on(keep, stream)
+
     def push_steps(self, t0: float, n_steps: int, particles: dict, stream=None) -> None:
         p, n, keep = make_particles(particles, device=self.device)
         if n_steps <= 0 or n % n_steps:

@@ -85,6 +85,7 @@ SIGNATURES = {
     "rad_push_step": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(Particles), _vp]),
     "rad_push_steps": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
                                       ctypes.POINTER(Particles), _vp]),
+    "rad_push_step_noalloc": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(Particles), _vp]),
     "rad_spectrum": (ctypes.c_int, [_vp, _dp, _vp]),
     "rad_spectrum_device": (ctypes.c_int, [_vp, _vp, _vp]),
     "rad_spectrum_complex": (ctypes.c_int, [_vp, _dp, _vp]),

@@ -100,6 +100,32 @@ void normal_basis(const double n[3], double e1[3], double e2[3])
     for (int c = 0; c < 3; ++c) e2[c] /= l2;
 }
 
+// ---- fixed scratch of the no-allocation push (rad_push_step_noalloc) ----------------
+// That entry point keeps its FP32 partial sums in this file-scope device array instead of
+// a grid's own buffers.  In host code the name `scratch` is only a host-side handle of the
+// symbol, not a device address: the array's address on each GPU is looked up once per
+// device (hipGetSymbolAddress, with that device current, when the first grid is created
+// on it) and only that address is ever passed to kernels.
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) float scratch[RAD_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+std::mutex g_scratch_mu;
+std::atomic<float*> g_scratch_addr[kScratchDevices];
+
+// Looks up the scratch address on the current device `dev` (once per device).
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(RAD_ERR_INVALID_ARG, "device %d beyond the %d devices the library supports", dev, kScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_addr[dev].load(std::memory_order_acquire)) return RAD_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(RAD_ERR_DEVICE, "no device address for the no-allocation scratch");
+    g_scratch_addr[dev].store(static_cast<float*>(p), std::memory_order_release);
+    return RAD_OK;
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -570,6 +596,10 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     }
 
     DeviceGuard dg(g->device);
+    if (int rs = scratch_setup(g->device)) {
+        free_grid(g);
+        return rs;
+    }
     const size_t sbytes = (size_t)points * 4 * sizeof(double);
     if (hipMalloc(&g->d_dirs9, dirs9.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&g->d_omega, om.size() * sizeof(double)) != hipSuccess ||
@@ -657,6 +687,49 @@ int rad_push_steps(rad_grid* g, double t0, int32_t n_steps, int64_t n_particles,
     if (rc) return rc;
     DeviceGuard dg(g->device);
     return push_range(g, t0, n_particles, (int64_t)n_steps * n_particles, p, (hipStream_t)stream);
+}
+
+int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_particles* p, void* stream)
+{
+    if (!g) return fail(RAD_ERR_INVALID_ARG, "grid is NULL");
+    if (n_particles < 0) return fail(RAD_ERR_INVALID_ARG, "n_particles < 0");
+    if (!std::isfinite(t)) return fail(RAD_ERR_INVALID_ARG, "t is not finite");
+    if (n_particles == 0) return RAD_OK;
+    int rc = check_particles(p);
+    if (rc) return rc;
+    const int64_t count = (int64_t)g->n_omega * g->n_dir * 4;        // FP32 values per split
+    const int64_t split_bytes = count * (int64_t)sizeof(float);
+    const int64_t cap_splits = (int64_t)(RAD_NOALLOC_SCRATCH_BYTES / (size_t)split_bytes);
+    if (cap_splits < 1)
+        return fail(RAD_ERR_INVALID_ARG,
+                    "grid of %lld points needs %lld B of partial sums, more than the %zu B no-allocation "
+                    "scratch (at most %zu points)", (long long)(count / 4), (long long)split_bytes,
+                    (size_t)RAD_NOALLOC_SCRATCH_BYTES, (size_t)RAD_NOALLOC_SCRATCH_BYTES / 16);
+    DeviceGuard dg(g->device);
+    float* scr = g->device >= 0 && g->device < kScratchDevices
+                     ? g_scratch_addr[g->device].load(std::memory_order_acquire) : nullptr;
+    if (!scr) return fail(RAD_ERR_DEVICE, "no-allocation scratch not set up on device %d", g->device);
+    hipStream_t st = (hipStream_t)stream;
+    // every fold of this grid runs in issue order: the ones already queued on its fold
+    // stream before the folds below, and later ones (and read-outs, resets) after them
+    if (int rc0 = after_folds(g, st)) return rc0;
+    const LaunchShape ls = shape_of(g->tile, g->variant);
+    const int nt = tiles_d(g) * tiles_w(g);
+    AccArgs a{};
+    fill_job(a.job, g, p, t, n_particles, g->tile);
+    a.part = scr;
+    rc = for_each_launch(a, n_particles, std::min<int64_t>(max_splits(g), cap_splits), [&]() -> int {
+        // same stream: a launch's accumulate rewrites the scratch only after the previous
+        // launch's fold has read it
+        hipError_t e = rad::launch_accumulate(a, p->dtype, g->precision, ls, (int)(a.splits * nt), st);
+        if (e != hipSuccess) return hip_fail(e, "accumulate launch");
+        e = rad::launch_fold(scr, g->d_S, a.splits, count, st);
+        if (e != hipSuccess) return hip_fail(e, "fold launch");
+        return RAD_OK;
+    });
+    if (rc) return rc;
+    RAD_HIP(hipEventRecord(g->ev_write, st));
+    return chain_fold_stream(g, g->ev_write);
 }
 
 int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream)
