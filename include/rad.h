@@ -216,10 +216,13 @@ int rad_set_tile(rad_grid* g, const rad_tile* t);
  * 0 is the uniform frequency grid with a 1-D shape.  Launch-shape tables key on it. */
 int rad_grid_variant(const rad_grid* g);
 
-/* Kernel timing of one grid.  While enabled, every accumulate launch and every fold
- * launch of the grid is bracketed by HIP events recorded on the launch's own stream.
- * rad_profile_read waits for the recorded events, returns the totals since the last read
- * (or enable) and clears them.  Enabling adds two event records per launch. */
+/* Kernel timing of one grid.  rad_profile_enable(g, k) with k >= 1 times every k-th
+ * accumulate launch of the grid and the fold launch that follows it (1: every launch; 0
+ * stops timing): the launches carry HIP start and stop events stamped by the launch itself
+ * on its own stream (hipExtLaunchKernel; no marker packets between launches; each timed
+ * launch still costs a few microseconds).  rad_profile_read waits for the recorded events,
+ * returns the totals of the timed launches since the last read (or enable) and clears
+ * them. */
 typedef struct rad_profile_stats {
     int64_t launches;        /* accumulate launches timed                               */
     int64_t updates;         /* particle x direction x frequency terms in those launches */

@@ -199,8 +199,11 @@ class Grid:
                                             _stream_handle(stream, self.device)))
 
     # ------------------------------------------------------------------ kernel timing
-    def profile(self, enable: bool = True) -> None:
-        _lib.check(_lib.lib().rad_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable=True) -> None:
+        """True (or 1): time every accumulate launch; an integer k > 1: every k-th one;
+        False / 0: stop timing."""
+        k = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        _lib.check(_lib.lib().rad_profile_enable(self._h, max(0, k)))
 
     def profile_read(self) -> dict:
         st = _lib.ProfileStats()

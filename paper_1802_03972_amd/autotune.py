@@ -150,18 +150,27 @@ def partial_bytes(c: dict, n_dir: int, n_omega: int, cus: int) -> int:
     return cus * c["wg_per_cu"] * td * to * 16
 
 
-def confirm(results, remeasure, rate, verbose: bool, top: int = 4, traffic=None, tie: float = 0.01):
-    """Second, longer pass over the fastest candidates of the sweep (single timings of a
-    sub-millisecond push vary by a few per cent): re-time the best `top` and rank them by
-    the longer measurement.  Among those within `tie` of the fastest, the one whose launch
+def confirm(results, remeasure, rate, verbose: bool, top: int = 6, traffic=None, tie: float = 0.02,
+            rounds: int = 3):
+    """Second, longer pass over the fastest candidates of the sweep: single timings of a
+    sub-millisecond push vary by a few per cent from run to run, so the best `top` are
+    re-timed in `rounds` interleaved rounds (candidate order rotated each round) and ranked
+    by their median.  Among those within `tie` of the fastest median, the one whose launch
     writes the fewest partial-sum bytes (`traffic(c)`) goes first."""
+    import statistics
     results = sorted(results, key=lambda r: r[0])
+    head = results[:top]
+    times = [[] for _ in head]
+    for r in range(rounds):
+        for i in range(len(head)):
+            k = (i + r) % len(head)
+            times[k].append(remeasure(head[k][1]))
     again = []
-    for ms0, c, _ in results[:top]:
-        ms = remeasure(c)
+    for (ms0, c, _), ts in zip(head, times):
+        ms = statistics.median(ts)
         again.append((ms, c, rate(ms)))
         if verbose:
-            print(f"  confirm {c}: {ms:.4f} ms (sweep {ms0:.4f})", flush=True)
+            print(f"  confirm {c}: median {ms:.4f} ms of {[round(t, 4) for t in ts]} (sweep {ms0:.4f})", flush=True)
     again.sort(key=lambda r: r[0])
     if traffic is not None and again:
         close = [r for r in again if r[0] <= again[0][0] * (1.0 + tie)]

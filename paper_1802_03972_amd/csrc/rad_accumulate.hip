@@ -26,6 +26,7 @@
 // * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
 //   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -389,13 +390,20 @@ inline hipError_t allow_lds(const void* kern, size_t lds, std::atomic<size_t>* a
 }
 
 template <typename InT, int PREC, int W, int DPW, int V>
-hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+hipError_t launch_acc_t(const AccArgs& a, const LaunchShape& s, int n_blocks, hipStream_t st,
+                        hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     auto kern = k_accumulate<InT, PREC, W, DPW, V>;
     const size_t lds = acc_lds_bytes(s);
     static std::atomic<size_t> lds_allowed[kMaxDevices] = {};   // per instantiation and device
     const hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds, lds_allowed);
     if (e != hipSuccess) return e;
+    if (ev_start || ev_stop) {
+        AccArgs arg = a;
+        void* args[] = {&arg};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), dim3(n_blocks), dim3(64 * s.waves), args, lds,
+                                  st, ev_start, ev_stop, 0);
+    }
     hipLaunchKernelGGL(kern, dim3(n_blocks), dim3(64 * s.waves), lds, st, a);
     return hipGetLastError();
 }
@@ -422,14 +430,15 @@ hipError_t launch_batch_t(const BatchArgs& b, const LaunchShape& s, int n_blocks
     return hipGetLastError();
 }
 
-// Dispatch on the launch shape; Fn<W, DPW>::run(...) is the templated launcher.
+// Dispatch on the launch shape to the templated launchers.
 template <typename InT, int PREC, typename A>
-hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStream_t st)
+hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStream_t st, hipEvent_t ev0,
+                          hipEvent_t ev1)
 {
 #define RAD_SHAPE_CASE(WW, DD, VV)                                                    \
     if (s.w_per_lane == WW && s.dir_per_wave == DD && s.variant == VV) {              \
         if constexpr (std::is_same<A, AccArgs>::value)                                \
-            return launch_acc_t<InT, PREC, WW, DD, VV>(a, s, n_blocks, st);           \
+            return launch_acc_t<InT, PREC, WW, DD, VV>(a, s, n_blocks, st, ev0, ev1); \
         else                                                                          \
             return launch_batch_t<InT, PREC, WW, DD, VV>(a, s, n_blocks, st);         \
     }
@@ -461,22 +470,22 @@ hipError_t dispatch_shape(const A& a, const LaunchShape& s, int n_blocks, hipStr
 
 template <typename A>
 hipError_t dispatch_all(const A& a, int dtype, int precision, const LaunchShape& s, int n_blocks,
-                        hipStream_t st)
+                        hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     if (dtype == 0) {
-        return precision == 0 ? dispatch_shape<float, 0>(a, s, n_blocks, st)
-                              : dispatch_shape<float, 1>(a, s, n_blocks, st);
+        return precision == 0 ? dispatch_shape<float, 0>(a, s, n_blocks, st, ev0, ev1)
+                              : dispatch_shape<float, 1>(a, s, n_blocks, st, ev0, ev1);
     }
-    return precision == 0 ? dispatch_shape<double, 0>(a, s, n_blocks, st)
-                          : dispatch_shape<double, 1>(a, s, n_blocks, st);
+    return precision == 0 ? dispatch_shape<double, 0>(a, s, n_blocks, st, ev0, ev1)
+                          : dispatch_shape<double, 1>(a, s, n_blocks, st, ev0, ev1);
 }
 
 }  // namespace
 
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
-                             int n_blocks, hipStream_t st)
+                             int n_blocks, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
-    return dispatch_all(a, dtype, precision, s, n_blocks, st);
+    return dispatch_all(a, dtype, precision, s, n_blocks, st, ev_start, ev_stop);
 }
 
 hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,

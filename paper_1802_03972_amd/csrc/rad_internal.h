@@ -98,11 +98,15 @@ inline size_t acc_lds_bytes(const LaunchShape& s)
 // Sets the calling thread's message returned by rad_last_error().
 void set_last_error(const char* msg);
 
-// Launchers (stream-ordered, return hipError_t).
+// Launchers (stream-ordered, return hipError_t).  Non-null ev_start / ev_stop are stamped
+// with the kernel's own start and end (hipExtLaunchKernel: no separate marker packets on
+// the stream, so timing does not slow the launch sequence down).
 hipError_t launch_accumulate(const AccArgs& a, int dtype, int precision, const LaunchShape& s,
-                             int n_blocks, hipStream_t st);
+                             int n_blocks, hipStream_t st, hipEvent_t ev_start = nullptr,
+                             hipEvent_t ev_stop = nullptr);
 // count = 4 * grid points (FP32 values per split); part is 16-byte aligned.
-hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st);
+hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 hipError_t launch_accumulate_batch(const Job* items, const int32_t* wg_seg_begin, const BatchSeg* segs,
                                    float* seg_part, int dtype, int precision,
                                    const LaunchShape& s, int n_blocks, hipStream_t st);

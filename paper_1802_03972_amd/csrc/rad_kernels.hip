@@ -2,6 +2,7 @@
 // accumulate kernels' FP32 partials, read-out (intensity and Cartesian spectrum), fills,
 // the tracked-particle (post-processing) kernels and a transcendental probe.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -365,12 +366,18 @@ hipError_t launch_fold_batch(const int32_t* n_jobs_dev, const FoldJob* jobs, int
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st)
+hipError_t launch_fold(const float* part, double* S, int splits, int64_t count, hipStream_t st,
+                       hipEvent_t ev_start, hipEvent_t ev_stop)
 {
-    const int64_t points = count / 4;
+    int64_t points = count / 4;
     if (points <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fold, dim3(grid1d(points, 256)), dim3(256), 0, st,
-                       reinterpret_cast<const f32x4*>(part), S, splits, points);
+    const f32x4* p4 = reinterpret_cast<const f32x4*>(part);
+    if (ev_start || ev_stop) {
+        void* args[] = {&p4, &S, &splits, &points};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(k_fold), dim3(grid1d(points, 256)), dim3(256), args,
+                                  0, st, ev_start, ev_stop, 0);
+    }
+    hipLaunchKernelGGL(k_fold, dim3(grid1d(points, 256)), dim3(256), 0, st, p4, S, splits, points);
     return hipGetLastError();
 }
 

@@ -154,14 +154,17 @@ struct rad_grid {
     double* d_omega = nullptr;
     float2* d_gtab = nullptr;
     double* d_S = nullptr;
-    // Two partial-sum buffers: the fold of push j (on fold_stream) overlaps the
-    // accumulate of push j+1 (on the caller's stream), which writes the other buffer.
+    // Two partial-sum buffers, used in turn: a push on one stream may start its
+    // accumulate while the fold of the previous push (issued on another stream) still
+    // reads the other buffer.
     float* d_part[2] = {nullptr, nullptr};
     int64_t part_splits = 0;
     int part_next = 0;
+    // Ordering point of every write of S: folds of single pushes are chained into it,
+    // batched folds and resets likewise; read-outs and later folds wait for its last event.
     hipStream_t fold_stream = nullptr;
-    hipEvent_t ev_acc_done[2] = {nullptr, nullptr};
     hipEvent_t ev_fold_done[2] = {nullptr, nullptr};
+    hipStream_t fold_done_on[2] = {nullptr, nullptr};   // stream each event was last recorded on
     hipEvent_t ev_write = nullptr;   // end of a write of S on a caller's stream (reset)
     bool fold_recorded[2] = {false, false};
     int last_fold = -1;
@@ -172,6 +175,8 @@ struct rad_grid {
     int variant = 0;           // rad::kVarDirect | rad::kVarShape3
     // kernel timing (rad_profile_*)
     bool profiling = false;
+    int64_t prof_period = 1;    // time every prof_period-th accumulate launch
+    int64_t prof_count = 0;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_acc, ev_fold;
     int64_t prof_updates = 0;
@@ -290,7 +295,6 @@ void free_grid(rad_grid* g)
     if (g->d_S) (void)hipFree(g->d_S);
     for (int b = 0; b < 2; ++b) {
         if (g->d_part[b]) (void)hipFree(g->d_part[b]);
-        if (g->ev_acc_done[b]) (void)hipEventDestroy(g->ev_acc_done[b]);
         if (g->ev_fold_done[b]) (void)hipEventDestroy(g->ev_fold_done[b]);
     }
     if (g->ev_write) (void)hipEventDestroy(g->ev_write);
@@ -376,10 +380,11 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
         const int b = g->part_next;
         g->part_next ^= 1;
         a.part = g->d_part[b];
-        // the fold that last read this buffer must be done before it is overwritten
-        if (g->fold_recorded[b]) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[b], 0));
+        // the fold that last read this buffer must be done before it is overwritten (stream
+        // order already guarantees it when that event was recorded on this stream)
+        if (g->fold_recorded[b] && g->fold_done_on[b] != st) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[b], 0));
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-        if (g->profiling) {
+        if (g->profiling && g->prof_count++ % g->prof_period == 0) {
             RAD_HIP(take_event(g, &e0));
             RAD_HIP(take_event(g, &e1));
             RAD_HIP(take_event(g, &e2));
@@ -387,18 +392,21 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
             g->ev_acc.emplace_back(e0, e1);
             g->ev_fold.emplace_back(e2, e3);
             g->prof_updates += (i1 - i0) * (int64_t)g->n_dir * g->n_omega;
-            RAD_HIP(hipEventRecord(e0, st));
         }
-        hipError_t e = rad::launch_accumulate(a, p->dtype, g->precision, ls, (int)(splits * nt), st);
+        hipError_t e = rad::launch_accumulate(a, p->dtype, g->precision, ls, (int)(splits * nt), st, e0, e1);
         if (e != hipSuccess) return hip_fail(e, "accumulate launch");
-        if (g->profiling) RAD_HIP(hipEventRecord(e1, st));
-        RAD_HIP(hipEventRecord(g->ev_acc_done[b], st));
-        RAD_HIP(hipStreamWaitEvent(g->fold_stream, g->ev_acc_done[b], 0));
-        if (g->profiling) RAD_HIP(hipEventRecord(e2, g->fold_stream));
-        e = rad::launch_fold(g->d_part[b], g->d_S, (int)splits, count, g->fold_stream);
+        // The fold runs right after the accumulate on the caller's stream, so it has the
+        // whole GPU for its few microseconds (beside the next push's accumulate it would
+        // trickle along in the few free wave slots).  It comes after every fold already
+        // issued for this grid, on whatever stream, and the grid's fold stream -- the
+        // ordering point of batched folds, resets and read-outs -- is chained behind it.
+        if (g->last_fold >= 0 && g->fold_done_on[g->last_fold] != st)
+            RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[g->last_fold], 0));
+        e = rad::launch_fold(g->d_part[b], g->d_S, (int)splits, count, st, e2, e3);
         if (e != hipSuccess) return hip_fail(e, "fold launch");
-        if (g->profiling) RAD_HIP(hipEventRecord(e3, g->fold_stream));
-        RAD_HIP(hipEventRecord(g->ev_fold_done[b], g->fold_stream));
+        RAD_HIP(hipEventRecord(g->ev_fold_done[b], st));
+        RAD_HIP(hipStreamWaitEvent(g->fold_stream, g->ev_fold_done[b], 0));
+        g->fold_done_on[b] = st;
         g->fold_recorded[b] = true;
         g->last_fold = b;
         return RAD_OK;
@@ -409,7 +417,8 @@ int push_range(rad_grid* g, double t0, int64_t n_per_step, int64_t total, const 
 // last one suffices).  Every call that touches the accumulator S on `st` does this first.
 int after_folds(rad_grid* g, hipStream_t st)
 {
-    if (g->last_fold >= 0) RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[g->last_fold], 0));
+    if (g->last_fold >= 0 && g->fold_done_on[g->last_fold] != st)
+        RAD_HIP(hipStreamWaitEvent(st, g->ev_fold_done[g->last_fold], 0));
     return RAD_OK;
 }
 
@@ -421,6 +430,7 @@ int chain_fold_stream(rad_grid* g, hipEvent_t ev)
     RAD_HIP(hipStreamWaitEvent(g->fold_stream, ev, 0));
     const int k = g->last_fold >= 0 ? g->last_fold : 0;
     RAD_HIP(hipEventRecord(g->ev_fold_done[k], g->fold_stream));
+    g->fold_done_on[k] = g->fold_stream;
     g->fold_recorded[k] = true;
     g->last_fold = k;
     return RAD_OK;
@@ -615,8 +625,6 @@ int rad_create_grid(rad_grid** out, const rad_grid_desc* d)
     int rc = ensure_partials(g);
     if (rc) { free_grid(g); return rc; }
     if (hipStreamCreateWithFlags(&g->fold_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&g->ev_acc_done[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&g->ev_acc_done[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_fold_done[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_fold_done[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&g->ev_write, hipEventDisableTiming) != hipSuccess) {
@@ -861,7 +869,9 @@ extern "C" int rad_profile_enable(rad_grid* g, int enable)
     DeviceGuard dg(g->device);
     release_events(g);
     g->prof_updates = 0;
-    g->profiling = enable != 0;
+    g->profiling = enable > 0;
+    g->prof_period = enable > 0 ? enable : 1;
+    g->prof_count = 0;
     return RAD_OK;
 }
 
