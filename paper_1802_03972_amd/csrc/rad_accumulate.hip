@@ -112,16 +112,21 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     for (int64_t c = c_begin; c < c_end; ++c) {
         // Stages 1-3 gate the workgroup's barriers: their waves get issue priority over the
         // hot loops of other workgroups on the CU (measured +2 %).  The hot loop itself runs
-        // one level above the default, i.e. above the fold of the previous push that shares
-        // the CUs (measured +0.3 %).
+        // one level above the default.
         __builtin_amdgcn_s_setprio(3);
+        // The set-up's per-thread offsets are derived from an opaque copy of the thread
+        // index in every chunk, so the compiler recomputes them (a few integer adds) instead
+        // of keeping them live across the hot loop, where the 4W accumulators leave no room
+        // for them (they were spilled to scratch memory).
+        int tc = threadIdx.x;
+        asm volatile("" : "+v"(tc));
         // 1. stage the chunk (SoA, coalesced), widened to FP64, plus the step time.
-        if (tid < P) {
-            const int64_t i = j.i_begin + c * P + tid;
+        if (tc < P) {
+            const int64_t i = j.i_begin + c * P + tc;
             const bool ok = i < j.i_end;
             const int64_t ii = ok ? i : j.i_begin;
 #pragma unroll
-            for (int f = 0; f < 10; ++f) raw[f * P + tid] = ok ? load_wide<InT>(j.f[f], ii) : 0.0;
+            for (int f = 0; f < 10; ++f) raw[f * P + tc] = ok ? load_wide<InT>(j.f[f], ii) : 0.0;
             // step = ii / n_per_step without a 64-bit integer division: the FP64 quotient of
             // two integers below 2^53 is within one of the true one; correct it exactly.
             int64_t step = 0;
@@ -130,13 +135,13 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 if (step * j.n_per_step > ii) --step;
                 else if ((step + 1) * j.n_per_step <= ii) ++step;
             }
-            raw[10 * P + tid] = ok ? j.t0 + (double)step * j.dt : 0.0;
-            const float N = ok ? (float)raw[9 * P + tid] : 0.f;
-            nw[tid] = make_float2(N, N * N);
+            raw[10 * P + tc] = ok ? j.t0 + (double)step * j.dt : 0.0;
+            const float N = ok ? (float)raw[9 * P + tc] : 0.f;
+            nw[tc] = make_float2(N, N * N);
         }
         __syncthreads();
         // 2. per (particle, direction) geometry.
-        for (int i = tid; i < P * TD; i += nt) {
+        for (int i = tc; i < P * TD; i += nt) {
             const int m = i / TD;
             int dg = td * TD + (i % TD);
             dg = dg < j.n_dir ? dg : j.n_dir - 1;
@@ -148,7 +153,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
         }
         // 3. per (particle, frequency) form-factor weight F = sqrt(N^2 g + N (1 - g)) (Eq. 12),
         //    FP32; frequencies outside the grid get F = 0 and contribute nothing.
-        for (int o = tid; o < (SHAPE3 ? 0 : TO); o += nt) {
+        for (int o = tc; o < (SHAPE3 ? 0 : TO); o += nt) {
             const int og = tw * TO + o;
             float2 g = make_float2(0.f, 0.f);
             if (og < j.n_omega) g = j.gtab[og];
@@ -279,13 +284,17 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
         __syncthreads();
     }
 
-    // 5. partial tile (coalesced over directions).
-    if (d < j.n_dir) {
-        const int o_loc = ob * W;
+    // 5. partial tile (coalesced over directions); the lane's place in it is recomputed
+    //    from an opaque thread index for the same reason as the set-up's offsets.
+    int te = threadIdx.x;
+    asm volatile("" : "+v"(te));
+    const int dl_e = (te & 63) % DPW;
+    const int o_loc = ((te >> 6) * SUBS + (te & 63) / DPW) * W;
+    if (td * TD + dl_e < j.n_dir) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-            if (o_first + k < j.n_omega)
-                out[(int64_t)(o_loc + k) * row + dl] = make_float4(s1r[k], s1i[k], s2r[k], s2i[k]);
+            if (tw * TO + o_loc + k < j.n_omega)
+                out[(int64_t)(o_loc + k) * row + dl_e] = make_float4(s1r[k], s1i[k], s2r[k], s2i[k]);
         }
     }
 }

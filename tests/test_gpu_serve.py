@@ -177,3 +177,54 @@ def test_continuous_batching(rad):
         Iref = oracle.spectrum(flatten(st, w.times()), w.directions()[ds], w.omegas()[ks], w.shape,
                                w.shape_len, w.dt)
         assert_parity(I[np.ix_(ds, ks)], Iref, f"served bunch n={w.n_particles} vs oracle", ks=ks)
+
+
+def test_serving_workload_poisson_trace(rad):
+    """The serving workload's own bunches and 128 x 512 grids, chunks arriving as its
+    Poisson process at the stated 2000 chunks/s (the first 400 arrivals; each bunch's chunks
+    are its successive time steps).  Every served spectrum equals the same chunks pushed
+    directly (FP32 rounding) and, on a direction x frequency sample, the oracle."""
+    import time
+    from workloads import serving_bunches, poisson_trace
+    ws = serving_bunches().bunches()
+    arrivals, which = poisson_trace(2000.0, 400, len(ws), seed=0)
+    n_per = [int(np.sum(which == b)) for b in range(len(ws))]
+    sts = [w.steps(0, max(1, n), workers=16) for w, n in zip(ws, n_per)]
+    grids = [grid_for(rad, w) for w in ws]
+    srv = rad.Server(hbm_budget=2 << 30, max_batch=64)
+    step_of = [0] * len(ws)
+    tickets = []
+    t0 = time.perf_counter()
+    for i in range(len(arrivals)):
+        while time.perf_counter() - t0 < arrivals[i]:
+            time.sleep(1e-4)
+        b = int(which[i])
+        j = step_of[b]
+        step_of[b] += 1
+        tickets.append(srv.submit(grids[b], float(ws[b].times(j, j + 1)[0]), host_chunk(sts[b], j)))
+    srv.drain()
+    stats = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(s["status"] == 0 for s in stats)
+    sizes = [s["batch_size"] for s in stats]
+    print(f"{len(stats)} chunks in {len(set(s['batch_id'] for s in stats))} batches, largest {max(sizes)}")
+    ds = np.arange(0, 128, 32)
+    ks = in_block_sample(512, 64)
+    for b, (w, g, st, n) in enumerate(zip(ws, grids, sts, n_per)):
+        if n == 0:
+            continue
+        part = {k: v[:n] for k, v in st.items()}
+        direct = grid_for(rad, w)
+        direct.push_steps(w.t0, n, to_device(part, "f32"))
+        I = g.spectrum()
+        # Both sides sum the same FP32 terms, grouped differently: one direct launch puts up to
+        # 32768 particles of many steps into each FP32 partial, the served batches fewer.  A
+        # recursive FP32 sum of n terms of random phase carries a rounding error of about
+        # 2^-24 sqrt(n / 2) of its magnitude (7.6e-6 at n = 32768), so 1e-5 rather than the
+        # 1e-6 of the few-chunk tests.
+        assert_close(I, direct.spectrum(), f"served bunch {b} (n={w.n_particles}, {n} chunks) vs direct pushes",
+                     tol_inf=1e-5, tol_freq=1e-5)
+        if w.n_particles <= 40000:
+            Iref = oracle.spectrum(flatten(part, w.times(0, n)), w.directions()[ds], w.omegas()[ks], w.shape,
+                                   w.shape_len, w.dt)
+            assert_parity(I[np.ix_(ds, ks)], Iref, f"served bunch {b} vs oracle", ks=ks)
