@@ -58,7 +58,7 @@ def parse(argv=None):
                     help="single_bunch_fp32: 'log' passes the frequencies as an explicit log-spaced list "
                          "(1e-4 * omega_max .. omega_max), evaluated with a per-term FP64 phase; 'blocklog' "
                          "spans the same range uniformly inside each block of 16 and log-like across "
-                         "blocks (recurrence with a per-block step)")
+                         "blocks (frequency walk with a per-block step)")
     ap.add_argument("--shape", default="", help="single_bunch_fp32: override the macro-particle shape "
                                                 "(e.g. cic3d for the direction-dependent cubic cell)")
     ap.add_argument("--tile", default="", help="override launch shape: w_per_lane,dir_per_wave,waves,wg_per_cu")
@@ -691,7 +691,7 @@ def bench_precision(args) -> dict:
     8x8 x 1024 frequencies to 1e20 rad/s, FP64 input.  Both arithmetic modes (FP64 geometry
     and phase with FP32 update; everything FP32) accumulate every step on the device; the
     FP64 oracle (the CPU-baseline leg) evaluates 4 directions x 13 frequencies (seeded and
-    recurrence bins) of the same sum, and both device spectra are compared with it there.
+    walked bins) of the same sum, and both device spectra are compared with it there.
     Steps are generated, pushed and handed to the oracle in groups of 250."""
     import numpy as np
     import torch

@@ -89,7 +89,7 @@ typedef struct rad_grid_desc {
                             The list is classified at creation (rad_grid_variant):
                             uniform to a few FP64 ulps -> the uniform grid; every aligned
                             block of 16 entries an arithmetic progression (piecewise-
-                            uniform) -> the frequency recurrence with a per-block step;
+                            uniform) -> the frequency walk with a per-block step;
                             otherwise each term's phase is evaluated from FP64.  Lists
                             that are not uniform use 16 frequencies per lane            */
 } rad_grid_desc;
@@ -212,7 +212,7 @@ int rad_set_tile(rad_grid* g, const rad_tile* t);
 /* Kernel variant chosen for a grid at creation, as bits (or a negative code):
  *   1  explicit frequency list, per-term FP64 phase
  *   2  direction-dependent (cubic-cell) shape factor
- *   4  piecewise-uniform frequency list, recurrence with a per-block step
+ *   4  piecewise-uniform frequency list, frequency walk with a per-block step
  * 0 is the uniform frequency grid with a 1-D shape.  Launch-shape tables key on it. */
 int rad_grid_variant(const rad_grid* g);
 

@@ -309,10 +309,10 @@ __device__ __forceinline__ int xcd_major_id(int b, int n)
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
 }
 
-// Waves per SIMD the 16-frequency recurrence kernels (uniform grid, per-block step) are
+// Waves per SIMD the 16-frequency walk kernels (uniform grid, per-block step) are
 // compiled for: 4 caps them at 128 VGPRs, so four waves share a SIMD (the issue rate of
-// this VALU-bound loop grows with resident waves; the few spills this costs sit in the
-// per-chunk set-up, not in the hot loop).  The other kernels keep the default for
+// this VALU-bound loop grows with resident waves; they fit without spills because the
+// set-up offsets are recomputed per chunk).  The other kernels keep the default for
 // 512-thread workgroups.
 #ifndef RAD_W16_WAVES
 #define RAD_W16_WAVES 4

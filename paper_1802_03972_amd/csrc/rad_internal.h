@@ -33,9 +33,9 @@ struct Job {
 
 // Kernel variant bits: how the phase is advanced along the lane's frequencies and where
 // the form factor comes from.
-constexpr int kVarDirect = 1;   // explicit frequency list: phase from FP64 per term (no recurrence)
+constexpr int kVarDirect = 1;   // explicit frequency list: phase from FP64 per term (no walk)
 constexpr int kVarShape3 = 2;   // direction-dependent shape factor g(n, omega)
-constexpr int kVarBlockStep = 4;  // piecewise-uniform list: recurrence with a per-block step
+constexpr int kVarBlockStep = 4;  // piecewise-uniform list: frequency walk with a per-block step
 // Frequencies per block of a piecewise-uniform list (= frequencies per lane of the variants).
 constexpr int kBlockW = 16;
 

@@ -448,7 +448,7 @@ int read_err_flag(rad_grid* g, hipStream_t st, int* flag)
 namespace {
 
 // Validated host-side tables of a grid description: directions with their normal basis
-// (n, e1, e2), the frequency list, the recurrence step, the Eq. 13 prefactor and the
+// (n, e1, e2), the frequency list, the walk step, the Eq. 13 prefactor and the
 // kernel variant.  check_shape = false skips the shape fields (chosen later).
 struct GridTables {
     std::vector<double> dirs9, om;
@@ -458,8 +458,8 @@ struct GridTables {
 };
 
 // How an explicit frequency list can be evaluated.  A list whose every aligned block of
-// kBlockW frequencies is an arithmetic progression (to a few FP64 ulps) runs the rotation
-// recurrence with a per-block step; if the steps also agree and the blocks continue one
+// kBlockW frequencies is an arithmetic progression (to a few FP64 ulps) runs the frequency
+// walk with a per-block step; if the steps also agree and the blocks continue one
 // another, the list is one uniform grid.  Otherwise each term takes its own FP64 phase.
 int classify_list(const std::vector<double>& om, std::vector<double>& bstep, double& domega)
 {

@@ -55,7 +55,7 @@ def test_batch_matches_oracle_and_single_pushes(rad):
         g1 = grid_for(rad, w)
         g1.push_steps(w.t0, w.n_steps, d)
         # the batch's tuned tile walks 16 frequencies per lane, the grid's 32: per-term
-        # recurrence rounding differs, so the per-frequency bound is the parity tolerance
+        # walk rounding differs, so the per-frequency bound is the parity tolerance
         assert_close(I, g1.spectrum(), f"batch n={w.n_particles} vs per-grid push", tol_freq=TOL)
 
 
@@ -117,7 +117,7 @@ def test_batch_mixes_grid_shapes_and_tiles(rad, grid_tiles, batch_tile):
         single = grid_for(rad, w)
         single.push_steps(w.t0, w.n_steps, d)
         # the batch may walk 32 frequencies per lane where the grid walks 16: per-term
-        # recurrence rounding differs, so the per-frequency bound is the parity tolerance
+        # walk rounding differs, so the per-frequency bound is the parity tolerance
         assert_close(g.spectrum(), single.spectrum(), "batched vs single push", tol_freq=TOL)
 
 

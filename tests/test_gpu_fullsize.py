@@ -1,8 +1,8 @@
 """Full-size parity on sampled outputs: the workloads' real particle counts, step counts and
 grids, launched as the bench launches them, checked against the oracle on a deterministic
 subset of (direction, frequency) points that the oracle evaluates one by one.  Sampled
-frequencies include, in blocks of 16, the lane's FP64-seeded first frequency and bins the
-three-term recurrence computes (offsets 7 and 15)."""
+frequencies include, in blocks of 16, the bins a lane reaches by walking from its
+FP64-seeded middle frequency (offsets 0, 7 and 15, up to eight products away)."""
 import time
 
 import numpy as np
@@ -52,7 +52,7 @@ PRECISION_KS = np.array([0, 1, 7, 15, 135, 271, 392, 519, 655, 776, 903, 1015, 1
 def test_precision_stress_all_10000_steps_from_one_picosecond(rad):
     """The precision-stress workload at its stated size: 16384 particles x 10000 steps from
     t = 1 ps on 64 x 1024 frequencies to 1e20 rad/s, FP64 input, in both arithmetic modes.
-    Oracle on 4 directions x 13 frequencies (seeded and recurrence bins, the highest
+    Oracle on 4 directions x 13 frequencies (walked bins of every kind, the highest
     included), summed as complex S over the same steps.  FP64 geometry and phase pass the
     gate; the all-FP32 variant loses the phase at high frequency and fails it."""
     import torch
@@ -89,8 +89,8 @@ def test_precision_stress_all_10000_steps_from_one_picosecond(rad):
 def test_batched_uneven_all_200_steps(rad):
     """The batched workload at its stated size: 12 bunches (log-uniform counts in
     [1e3, 5e5]), 200 distinct time steps, one batched persistent launch per step over all
-    bunches.  Every bunch against the oracle on 3 directions x 7 frequencies (seeded and
-    recurrence bins), summed over all 200 steps."""
+    bunches.  Every bunch against the oracle on 3 directions x 7 frequencies (near and far
+    walked bins), summed over all 200 steps."""
     import torch
     mb = batched_uneven()
     ws = mb.bunches()

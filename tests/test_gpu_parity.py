@@ -246,7 +246,7 @@ def test_coherent_and_incoherent_limits_gpu(rad):
 def test_single_bunch_full_size_sampled(rad):
     """One full-size step of the 65536-particle single-bunch workload (launch shape of the
     bench), checked against the oracle on every direction and, in every block of 16
-    frequencies, the seeded one and two taken from the recurrence."""
+    frequencies, offsets 0, 7 and 15 (walked eight, one and seven products from the seed)."""
     w = SINGLE.scaled(n_steps=1)
     st = w.steps()
     I = run_gpu(rad, w, st).spectrum()
@@ -357,8 +357,10 @@ def test_device_readout_is_ordered_before_later_reset_and_push(rad):
 
 
 def test_recurrence_with_steps_near_zero_and_pi(rad):
-    """The three-term frequency recurrence loses the most accuracy when the per-frequency
-    phase step domega*tau is close to a multiple of pi (2 cos(theta) near +-2).  Particles
+    """A frequency recurrence loses the most accuracy when the per-frequency phase step
+    domega*tau is close to a multiple of pi: the three-term form 2 cos(theta) z_k - z_{k-1}
+    drifts there (the rounding of 2 cos(theta) is divided by sin(theta)); the kernel's
+    complex-product walk must not.  Particles
     are placed so that on the axis the step is within 1e-7..1e-2 rad of 0 or pi (and within
     ~0.02 rad of it on the tilted directions); three steps a whole number of step periods
     apart."""

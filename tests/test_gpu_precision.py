@@ -1,9 +1,9 @@
 """Precision at large t and high omega (reduced precision-stress workload): the FP64-phase
 path stays within 1e-4 of the FP64 oracle, also frequency by frequency, including the bins
-the three-term recurrence computes (offsets 7 and 15 in a block of 16); the all-FP32
+a lane walks to from its seed (offsets 0, 7 and 15 in a block of 16); the all-FP32
 variant misses the gate (its FP32 1 - beta.n) and loses the phase at high frequency (FP32
-t - n.r/c at t = 1 ps is off by ~1e-19 s, ~10 rad at 1e20 rad/s), on seeded and
-recurrence bins alike."""
+t - n.r/c at t = 1 ps is off by ~1e-19 s, ~10 rad at 1e20 rad/s), on near and
+far walked bins alike."""
 import numpy as np
 import pytest
 
@@ -40,7 +40,7 @@ def test_fp64_phase_vs_all_fp32_at_one_picosecond(rad):
     print("all FP32 at 1 ps:", rep)
     assert rep["e_inf"] > 1e-3
     assert rep["per_frequency_max_top_quarter"] > 0.1
-    # the loss shows on the recurrence bins as on the seeded ones
+    # the loss shows on near and far walked bins alike
     hi = sel >= 3 * w.n_omega // 4
     for m in (0, 7, 15):
         cols = hi & (sel % 16 == m)

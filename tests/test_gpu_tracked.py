@@ -46,7 +46,7 @@ def test_tracked_equals_in_situ_and_oracle(rad):
     g.push_steps(w.t0, w.n_steps, to_device(st, "f32"))
     Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
     # 8 frequencies per thread in the tracked kernel, 16 per lane in the in-situ one: the
-    # recurrences are seeded at different frequencies
+    # walks are seeded at different frequencies
     assert_close(I, g.spectrum(), "tracked vs in-situ", tol_inf=1e-5, tol_freq=TOL)
     assert_parity(I, Iref, "tracked vs oracle")
 
