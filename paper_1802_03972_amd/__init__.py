@@ -242,7 +242,8 @@ class Batcher:
 
     def set_tile(self, **kw) -> None:
         """Launch shape of the batched kernel (all four fields), or no arguments to restore
-        the default."""
+        the default.  An explicit choice replaces a pending tile="auto" lookup."""
+        self._auto = False
         if not kw:
             _lib.check(_lib.lib().rad_batcher_set_tile(self._h, None))
             return
@@ -327,7 +328,9 @@ class Server:
             self.set_tile(**tile)
 
     def set_tile(self, **kw) -> None:
-        """Launch shape of the batched launches (all four fields), or none for the default."""
+        """Launch shape of the batched launches (all four fields), or none for the default.
+        An explicit choice replaces a pending tile="auto" lookup."""
+        self._auto = False
         if not kw:
             _lib.check(_lib.lib().rad_server_set_tile(self._h, None))
             return

@@ -204,7 +204,7 @@ def tune_batch(n_dir: int, n_omega: int, counts, dtype: str = "f32", precision: 
     parts = [synthetic_particles(int(n), dtype, device, seed=k) for k, n in enumerate(counts)]
     grids = [Grid(dirs, 0.0, 1e19 / max(1, n_omega - 1), n_omega, shape="cic", shape_len=1e-7, dt=5e-17,
                   precision=precision, device=device, tile=None) for _ in counts]
-    b = Batcher(device=device, max_items=len(counts))
+    b = Batcher(device=device, max_items=len(counts), tile=None)
     stream = torch.cuda.current_stream(device)
     total = float(sum(counts)) * n_dir * n_omega
     results = []

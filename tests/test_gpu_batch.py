@@ -121,6 +121,26 @@ def test_batch_mixes_grid_shapes_and_tiles(rad, grid_tiles, batch_tile):
         assert_close(g.spectrum(), single.spectrum(), "batched vs single push", tol_freq=TOL)
 
 
+def test_explicit_batch_tile_wins_over_auto(rad):
+    """A Batcher created with tile="auto" looks its launch shape up at the first push; a
+    shape set explicitly before that push must not be replaced by the lookup (the autotuner
+    times each candidate this way)."""
+    from paper_1802_03972_amd.autotune import lookup_batch
+    w = SINGLE.scaled(n_particles=2000, n_steps=1, nx_dir=8, ny_dir=8, n_omega=256, seed=44)
+    g = grid_for(rad, w)
+    auto = lookup_batch(g.n_dir, g.n_omega, g.precision)
+    assert auto is not None, "the tuned table has a batched entry for 64 x 256"
+    mine = dict(w_per_lane=16, dir_per_wave=16, waves=4, wg_per_cu=3)
+    assert mine != auto
+    b = rad.Batcher()
+    b.set_tile(**mine)
+    b.push([(g, w.t0, w.n_steps, to_device(w.steps(), w.in_dtype))])
+    assert b.get_tile() == mine
+    b2 = rad.Batcher()
+    b2.push([(grid_for(rad, w), w.t0, w.n_steps, to_device(w.steps(), w.in_dtype))])
+    assert b2.get_tile() == auto
+
+
 def test_batch_rejects_mixed_precision(rad):
     bs = bunches([100, 100], steps=1)
     g0 = grid_for(rad, bs[0][0])
