@@ -280,10 +280,10 @@ def bench_single(args, name: str) -> dict:
     torch.cuda.synchronize()
     log("[bench] warmup done")
 
-    # ---- timed region: kernel start/stop events stamped by every 4th accumulate launch
+    # ---- timed region: kernel start/stop events stamped by every 10th accumulate launch
     # (and the fold after it) on the launch stream while it runs (events on every launch
     # cost 2 % of the whole-job time; every launch does the same work)
-    g.profile(4)
+    g.profile(10)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
