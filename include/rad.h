@@ -22,10 +22,11 @@
  *    available from rad_last_error() (per calling thread) and outputs are untouched.
  *  - `stream` is a hipStream_t passed as void*; NULL means the device's null stream.
  *    All work is stream-ordered.  Calls on one grid come from one host thread at a time.
- *    The library orders every update of a grid's accumulator itself (all folds run on
- *    the grid's own stream, batched folds are chained into it, and read-outs wait for
- *    the last fold, resets are chained into it), so pushes, resets and read-outs may be
- *    issued on different streams and take effect in the order they are issued.
+ *    The library orders every update of a grid's accumulator itself (a push's fold runs
+ *    on the caller's stream after the grid's previous fold; batched folds, resets and
+ *    device read-outs wait for the last fold and become the new last write, which later
+ *    calls on other streams wait for), so pushes, resets and read-outs may be issued on
+ *    different streams and take effect in the order they are issued.
  *  - Device pointers are plain device addresses on the grid's device, caller-owned.
  *  - Units are SI: r [m], beta [1], dbeta/dt [1/s], N [electrons, real >= 0],
  *    t and dt [s], omega [rad/s], shape length [m].
