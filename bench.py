@@ -187,7 +187,9 @@ def main() -> int:
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    import paper_1802_03972_amd  # noqa: F401  (fails loudly if the HIP library is not built)
+    from paper_1802_03972_amd.build import ensure_built
+    ensure_built()    # a built library is used as is; none in the tree: build it first
+    import paper_1802_03972_amd  # noqa: F401
 
     runners = {"single_bunch_fp32": lambda: bench_single(args, "single_bunch_fp32"),
                "tiny_fp64": lambda: bench_single(args, "tiny_fp64"),

@@ -79,6 +79,14 @@ def build(verbose: bool = False, extra_flags=()) -> str:
     return LIB
 
 
+def ensure_built(verbose: bool = False) -> str:
+    """The in-tree library (and the C-ABI test harness) as it is, built first only if it is
+    not there (after a source change, call build())."""
+    if not os.path.exists(LIB) or not os.path.exists(C_DEMO):
+        build(verbose)
+    return LIB
+
+
 C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi", "rad_c_demo.c")
 C_DEMO = os.path.join(ROOT, "tests", "c_abi", "rad_c_demo")
 

@@ -18,7 +18,8 @@ DEMO = os.path.join(ROOT, "tests", "c_abi", "rad_c_demo")
 
 @pytest.mark.parametrize("shape,shape_id", [("gauss", 4), ("cic", 1)])
 def test_c_program_matches_oracle(tmp_path, shape, shape_id):
-    assert os.path.exists(DEMO), "build the C harness first (paper_1802_03972_amd/build.py)"
+    from paper_1802_03972_amd.build import ensure_built
+    ensure_built()    # library and harness as built; built first only if absent
     w = TINY.scaled(n_particles=300, n_steps=5, shape=shape, seed=61)
     st = w.steps()
     dirs = w.directions()
@@ -38,6 +39,8 @@ def test_c_program_matches_oracle(tmp_path, shape, shape_id):
 
 def test_c_program_reports_errors(tmp_path):
     """A bad argument reaches rad_last_error() and a non-zero exit status."""
+    from paper_1802_03972_amd.build import ensure_built
+    ensure_built()
     w = TINY.scaled(n_particles=8, n_steps=1, seed=62)
     st = w.steps()
     blob = np.concatenate([np.ascontiguousarray(st[k], np.float64).reshape(-1) for k in FIELDS]

@@ -17,6 +17,8 @@ def rad():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_1802_03972_amd as rad
+    from paper_1802_03972_amd.build import ensure_built
+    ensure_built()    # a built library is used as is
     rad._lib.lib()
     return rad
 
