@@ -152,6 +152,26 @@ def parity_entry(I, Iref, ks, sample: str) -> dict:
     return rep
 
 
+def rounding_entry(w, n_steps: int, om_stride: int) -> dict:
+    """How much the FP32 rounding of the input trajectory alone moves the spectrum: the
+    oracle on the FP64 trajectory against the oracle on its FP32 rounding (what the device
+    ingests), over the first n_steps steps of bunch w and every om_stride-th frequency."""
+    import numpy as np
+    import oracle
+    from oracle.metrics import error_report
+    from workloads import flatten, stack_steps
+    wn = w.scaled(n_steps=n_steps)
+    exact = stack_steps(wn.bunch(), wn.times())
+    rounded = {k: v.astype(np.float32).astype(np.float64) for k, v in exact.items()}
+    om = wn.omegas()[::om_stride]
+    I_exact = oracle.spectrum(flatten(exact, wn.times()), wn.directions(), om, wn.shape, wn.shape_len, wn.dt)
+    I_round = oracle.spectrum(flatten(rounded, wn.times()), wn.directions(), om, wn.shape, wn.shape_len, wn.dt)
+    rep = error_report(I_round, I_exact)
+    rep["sample"] = (f"{wn.n_particles} particles x {n_steps} steps, {wn.n_dir} directions x every "
+                     f"{om_stride}th of {w.n_omega} frequencies")
+    return rep
+
+
 def cpu_entry(updates: float, seconds: float, sample: str, **extra) -> dict:
     import oracle
     out = {"value": updates / seconds, "unit": "updates/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -360,17 +380,7 @@ def bench_single(args, name: str) -> dict:
         log(f"[bench] parity on the sample: e_inf {parity['e_inf']:.3e}, per-frequency "
             f"{parity['per_frequency_max']:.3e}, pass {parity['pass']}")
         if big and om_list is None and not args.shape:
-            # input rounding: oracle on the FP64 trajectory vs on its FP32 rounding (4 steps,
-            # every 16th frequency)
-            from oracle.metrics import error_report
-            from workloads import stack_steps
-            w4 = w.scaled(n_steps=4)
-            exact = stack_steps(w4.bunch(), w4.times())
-            rounded = {k: v.astype(np.float32).astype(np.float64) for k, v in exact.items()}
-            om = w4.omegas()[::16]
-            I_exact = oracle.spectrum(flatten(exact, w4.times()), w4.directions(), om, w4.shape, w4.shape_len, w4.dt)
-            I_round = oracle.spectrum(flatten(rounded, w4.times()), w4.directions(), om, w4.shape, w4.shape_len, w4.dt)
-            rounding = error_report(I_round, I_exact)
+            rounding = rounding_entry(w, 4, 16)
 
     g.close()
     return {
@@ -552,6 +562,8 @@ def bench_batched(args) -> dict:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "input_rounding_fp32_vs_fp64_trajectory": (
+            None if args.no_cpu_baseline else rounding_entry(ws[int(np.argmax([v.n_particles for v in ws]))], 2, 16)),
     }
 
 
@@ -685,6 +697,7 @@ def bench_serving(args) -> dict:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "input_rounding_fp32_vs_fp64_trajectory": None if args.no_cpu_baseline else rounding_entry(ws[2], 8, 16),
     }
 
 
