@@ -160,8 +160,9 @@ struct rad_grid {
     float* d_part[2] = {nullptr, nullptr};
     int64_t part_splits = 0;
     int part_next = 0;
-    // Ordering point of every write of S: folds of single pushes are chained into it,
-    // batched folds and resets likewise; read-outs and later folds wait for its last event.
+    // Ordering hub of the writes of S: every single-push fold (run on the pushing stream),
+    // batched fold, reset and device read-out is chained into it; a call on another stream
+    // than the last write's waits for its last event.
     hipStream_t fold_stream = nullptr;
     hipEvent_t ev_fold_done[2] = {nullptr, nullptr};
     hipStream_t fold_done_on[2] = {nullptr, nullptr};   // stream that orders the write each event marks
@@ -724,8 +725,8 @@ int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_
                      ? g_scratch_addr[g->device].load(std::memory_order_acquire) : nullptr;
     if (!scr) return fail(RAD_ERR_DEVICE, "no-allocation scratch not set up on device %d", g->device);
     hipStream_t st = (hipStream_t)stream;
-    // every fold of this grid runs in issue order: the ones already queued on its fold
-    // stream before the folds below, and later ones (and read-outs, resets) after them
+    // every fold of this grid runs in issue order: the folds below come after every fold
+    // already issued (on any stream), later folds, read-outs and resets after them
     if (int rc0 = after_folds(g, st)) return rc0;
     const LaunchShape ls = shape_of(g->tile, g->variant);
     const int nt = tiles_d(g) * tiles_w(g);
@@ -754,8 +755,8 @@ int rad_spectrum_device(rad_grid* g, double* I_dev, void* stream)
     if (int rc0 = after_folds(g, st)) return rc0;
     hipError_t e = rad::launch_finalize(g->d_S, I_dev, g->n_dir, g->n_omega, g->C, st);
     if (e != hipSuccess) return hip_fail(e, "finalize launch");
-    // The read-out does not synchronise: later folds (on the fold stream) and resets (on
-    // any stream, which wait for the last fold) must not write S before it has been read.
+    // The read-out does not synchronise: later folds and resets, on any stream, must not
+    // write S before it has been read, so the read-out becomes the grid's last-write mark.
     RAD_HIP(hipEventRecord(g->ev_write, st));
     return chain_fold_stream(g, g->ev_write, st);
 }
@@ -1332,8 +1333,8 @@ extern "C" int rad_batcher_push(rad_batcher* b, const rad_batch_item* items, int
         sl.used = true;
         last_done = sl.done;
     }
-    // Later single-grid folds (on each grid's fold stream, whatever stream pushes them) and
-    // read-outs must come after this batch's fold: chain each grid's fold stream behind it.
+    // Later single-grid folds (on whatever stream pushes them), resets and read-outs must
+    // come after this batch's fold: chain each grid's fold stream behind it.
     if (last_done) {
         std::vector<rad_grid*> seen;
         for (const auto& in : info) {
