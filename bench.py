@@ -200,9 +200,9 @@ def main() -> int:
         return calibrate_copy(args.calibrate_copy)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the spectrum would shard by particles with one reduction of the complex spectrum, "
-              "which is not part of this build.", file=sys.stderr)
+              "which is not implemented.", file=sys.stderr)
         return 2
 
     import torch
