@@ -11,7 +11,7 @@ from tests.helpers import assert_parity, to_device
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-N_CASES = 16
+N_CASES = 48
 
 
 @pytest.fixture(scope="module")
