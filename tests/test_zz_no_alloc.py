@@ -71,6 +71,28 @@ def test_noalloc_push_equals_push_step_twice(rad):
     assert L.RAD_OK == 0
 
 
+def test_noalloc_at_the_scratch_limit(rad):
+    """A grid of exactly RAD_NOALLOC_SCRATCH_BYTES / 16 points (2048 directions x 2048
+    frequencies): one particle split per launch, and a push of more particles than one split
+    holds takes two launches, each folded before the scratch is reused."""
+    w = SINGLE.scaled(n_particles=40000, n_steps=1, nx_dir=32, ny_dir=64, n_omega=2048, seed=74)
+    assert w.n_dir * w.n_omega * 16 == 64 << 20
+    st = w.steps()
+    a = pushed(rad, w, st, noalloc=True)
+    b = pushed(rad, w, st, noalloc=False)
+    what = f"no-alloc push at the limit, {w.n_dir} x {w.n_omega}, {w.n_particles} particles"
+    # the scratch path sums at most 32768 particles per FP32 split; an allocating push may
+    # cut other splits (on this grid's 512 tiles it also takes one per launch): FP32
+    # rounding of sums over 32768 terms of random phase, about 2^-24 sqrt(32768 / 2) =
+    # 7.6e-6 of their size, bounds the difference
+    Ia = a.spectrum()
+    assert_close(Ia, b.spectrum(), what + " vs rad_push_step", tol_inf=1e-5, tol_freq=1e-5)
+    ds = np.arange(0, w.n_dir, 511)
+    ks = in_block_sample(w.n_omega, 64)
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions()[ds], w.omegas()[ks], w.shape, w.shape_len, w.dt)
+    assert_parity(Ia[np.ix_(ds, ks)], Iref, what + " vs oracle", ks=ks)
+
+
 def test_noalloc_rejects_grid_beyond_scratch(rad):
     w = SINGLE.scaled(n_particles=64, n_steps=1, nx_dir=32, ny_dir=64, n_omega=2049, seed=73)
     g = grid_for(rad, w)          # 2048 x 2049 points need 16 B each per split: > 64 MiB
