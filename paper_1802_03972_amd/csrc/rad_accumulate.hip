@@ -79,10 +79,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     static_assert(!BSTEP || W == kBlockW, "block steps are defined per 16 frequencies");
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
-    const double om_first = j.omega[o_first < j.n_omega ? o_first : j.n_omega - 1];
+    const double om_first = gload(j.omega, o_first < j.n_omega ? o_first : j.n_omega - 1);
     // piecewise-uniform list: this lane's block spacing (the lane's frequencies are one block)
     double bstep = 0.0;
-    if constexpr (BSTEP) bstep = j.bstep[(o_first < j.n_omega ? o_first : j.n_omega - 1) / kBlockW];
+    if constexpr (BSTEP) bstep = gload(j.bstep, (o_first < j.n_omega ? o_first : j.n_omega - 1) / kBlockW);
     // The lane's W frequencies are walked from one FP64-seeded frequency by complex
     // products with the rotation w = exp(i domega tau).  The seed is the middle of the block
     // (index KS = W/2, on the block's own progression), and the walk goes forward and
@@ -98,8 +98,8 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const int oc = o_first + k < j.n_omega ? o_first + k : j.n_omega - 1;
-            if constexpr (DIRECT) om[k] = j.omega[oc];
-            if constexpr (SHAPE3) gl[k] = j.g3[(int64_t)dc * j.n_omega + oc];
+            if constexpr (DIRECT) om[k] = gload(j.omega, oc);
+            if constexpr (SHAPE3) gl[k] = gload(j.g3, (int64_t)dc * j.n_omega + oc);
         }
     }
 
@@ -156,7 +156,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
         for (int o = tc; o < (SHAPE3 ? 0 : TO); o += nt) {
             const int og = tw * TO + o;
             float2 g = make_float2(0.f, 0.f);
-            if (og < j.n_omega) g = j.gtab[og];
+            if (og < j.n_omega) {
+                const float* gt = reinterpret_cast<const float*>(j.gtab);
+                g = make_float2(gload(gt, 2 * (int64_t)og), gload(gt, 2 * (int64_t)og + 1));
+            }
             float* dst = ff + o;
 #pragma unroll 8
             for (int m = 0; m < P; ++m, dst += TO) {

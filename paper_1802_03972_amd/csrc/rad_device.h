@@ -56,10 +56,22 @@ __device__ __forceinline__ void flag_error(int* err)
     atomicOr(err, 1);
 }
 
+// Reads p[i] from device (global) memory.  A pointer that reaches a kernel inside a
+// structure loaded from memory (the batched kernel's per-item jobs) is generic to the
+// compiler, which then emits flat loads; a flat load also counts against the LDS wait
+// counter, so every LDS wait of the set-up stages would wait for the HBM reads too.  The
+// cast states the address space (a no-op for pointers that are kernel arguments).  T is
+// a scalar type (vector class types cannot be copied out of another address space).
+template <typename T>
+__device__ __forceinline__ T gload(const T* p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
 template <typename InT>
 __device__ __forceinline__ double load_wide(const void* p, int64_t i)
 {
-    return static_cast<double>(static_cast<const InT*>(p)[i]);
+    return static_cast<double>(gload(static_cast<const InT*>(p), i));
 }
 
 // Per (particle, direction) geometry.  Writes A1, A2 (FP32), w = exp(i domega tau) and
@@ -74,9 +86,9 @@ __device__ __forceinline__ void particle_direction_setup(const double* __restric
     const double bx = raw[3 * P + m], by = raw[4 * P + m], bz = raw[5 * P + m];
     const double dbx = raw[6 * P + m], dby = raw[7 * P + m], dbz = raw[8 * P + m];
     const double N = raw[9 * P + m], t = raw[10 * P + m];
-    const double nx = dv[0], ny = dv[1], nz = dv[2];
-    const double e1x = dv[3], e1y = dv[4], e1z = dv[5];
-    const double e2x = dv[6], e2y = dv[7], e2z = dv[8];
+    const double nx = gload(dv, 0), ny = gload(dv, 1), nz = gload(dv, 2);
+    const double e1x = gload(dv, 3), e1y = gload(dv, 4), e1z = gload(dv, 5);
+    const double e2x = gload(dv, 6), e2y = gload(dv, 7), e2z = gload(dv, 8);
     float A1, A2, wr, wi;
     double ph;
     bool bad;
