@@ -156,7 +156,10 @@ int rad_push_steps(rad_grid* g, double t0, int32_t n_steps, int64_t n_particles,
  * by FP32 rounding of the partial sums).  Kernel timing (rad_profile_*) does not cover it.
  * All calls on one GPU share the scratch and leave their partial sums in it: calls that
  * can overlap on one GPU (issued on different streams with no ordering between them)
- * race and give wrong results; order them on one stream. */
+ * race and give wrong results; order them on one stream.
+ * Under HIP stream capture the call records no event and waits on none, so the captured
+ * kernels carry no ordering against the grid's other work: capture after that work has
+ * completed and replay on the stream that issues the grid's other calls. */
 #define RAD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_particles* p,
                           void* stream);

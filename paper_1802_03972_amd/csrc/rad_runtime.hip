@@ -725,9 +725,17 @@ int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_
                      ? g_scratch_addr[g->device].load(std::memory_order_acquire) : nullptr;
     if (!scr) return fail(RAD_ERR_DEVICE, "no-allocation scratch not set up on device %d", g->device);
     hipStream_t st = (hipStream_t)stream;
+    // Under stream capture the call records no event and waits on none (a wait on an event
+    // recorded outside the capture, or another stream waiting on the capture, would break
+    // it): the caller orders the captured push against the grid's other work.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    RAD_HIP(hipStreamIsCapturing(st, &cap));
+    const bool capturing = cap != hipStreamCaptureStatusNone;
     // every fold of this grid runs in issue order: the folds below come after every fold
     // already issued (on any stream), later folds, read-outs and resets after them
-    if (int rc0 = after_folds(g, st)) return rc0;
+    if (!capturing) {
+        if (int rc0 = after_folds(g, st)) return rc0;
+    }
     const LaunchShape ls = shape_of(g->tile, g->variant);
     const int nt = tiles_d(g) * tiles_w(g);
     AccArgs a{};
@@ -743,6 +751,7 @@ int rad_push_step_noalloc(rad_grid* g, double t, int64_t n_particles, const rad_
         return RAD_OK;
     });
     if (rc) return rc;
+    if (capturing) return RAD_OK;
     RAD_HIP(hipEventRecord(g->ev_write, st));
     return chain_fold_stream(g, g->ev_write, st);
 }

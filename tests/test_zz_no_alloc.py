@@ -93,6 +93,36 @@ def test_noalloc_at_the_scratch_limit(rad):
     assert_parity(Ia[np.ix_(ds, ks)], Iref, what + " vs oracle", ks=ks)
 
 
+def test_noalloc_push_under_graph_capture(rad):
+    """Captured into a graph (the call records no event under capture), the no-alloc push
+    replays bitwise equal to the same push issued directly, over several replays with eager
+    work, resets and synchronisation between them (no memset is recorded: the kernels
+    write every partial they read)."""
+    import torch
+    w = SINGLE.scaled(n_particles=3000, n_steps=1, nx_dir=4, ny_dir=8, n_omega=64, seed=75)
+    st = w.steps()
+    part = step_slice(to_device(st, w.in_dtype), 0, w.n_particles)
+    t = float(w.times()[0])
+    g = grid_for(rad, w)
+    g.push_step_noalloc(t, part)
+    ref = g.spectrum()
+    g.reset()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.push_step_noalloc(t, part)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.reset()
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.spectrum(), ref), rep
+        del junk
+    Iref = oracle.spectrum(flatten(st, w.times()), w.directions(), w.omegas(), w.shape, w.shape_len, w.dt)
+    assert_parity(ref, Iref, "no-alloc push (captured and replayed) vs oracle")
+
+
 def test_noalloc_rejects_grid_beyond_scratch(rad):
     w = SINGLE.scaled(n_particles=64, n_steps=1, nx_dir=32, ny_dir=64, n_omega=2049, seed=73)
     g = grid_for(rad, w)          # 2048 x 2049 points need 16 B each per split: > 64 MiB
