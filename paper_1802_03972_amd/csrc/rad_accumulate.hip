@@ -20,9 +20,11 @@
 //        shared by the workgroup's TD directions;
 //     4. the hot loop: per particle, each lane seeds z = exp(i omega tau) at the middle
 //        frequency of its block from the FP64 phase (reduced to [0, 1) revolutions before
-//        leaving FP64), then walks its W frequencies forward and backward by complex
-//        products with w (uniform omega steps), scaling by F and accumulating.  10 FP32 VALU
-//        operations per update: 2 (scale) + 4 (two complex multiply-adds) + 4 (rotation).
+//        leaving FP64), then walks its W frequencies forward and backward from it, scaling
+//        by F and accumulating.  On a uniform grid with 16 frequencies per lane the walk is
+//        the three-term recurrence z_{k+1} = 2 cos(theta) z_k - z_{k-1}: 8 FP32 VALU
+//        operations per update, 2 (scale) + 4 (two complex multiply-adds) + 2 (recurrence).
+//        Other layouts walk by complex products with w: 10 per update (4 for the rotation).
 // * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
 //   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
 
@@ -77,17 +79,20 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     constexpr bool BSTEP = (V & kVarBlockStep) != 0;
     static_assert(!(DIRECT && BSTEP), "a frequency list is either direct or block-stepped");
     static_assert(!BSTEP || W == kBlockW, "block steps are defined per 16 frequencies");
+    // uniform grid, 1-D shape, FP64 geometry, 16 frequencies per lane: the walk is the
+    // three-term recurrence from the mid-block seed (at most 7 steps from it)
+    constexpr bool TT = (V == 0) && (W == 16) && (PREC == 0);
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
     const double om_first = gload(j.omega, o_first < j.n_omega ? o_first : j.n_omega - 1);
     // piecewise-uniform list: this lane's block spacing (the lane's frequencies are one block)
     double bstep = 0.0;
     if constexpr (BSTEP) bstep = gload(j.bstep, (o_first < j.n_omega ? o_first : j.n_omega - 1) / kBlockW);
-    // The lane's W frequencies are walked from one FP64-seeded frequency by complex
-    // products with the rotation w = exp(i domega tau).  The seed is the middle of the block
-    // (index KS = W/2, on the block's own progression), and the walk goes forward and
-    // backward from it, so no frequency is more than W/2 products from its seed (the
-    // rounding of w accumulates once per product).
+    // The lane's W frequencies are walked from one FP64-seeded frequency with the rotation
+    // w = exp(i domega tau).  The seed is the middle of the block (index KS = W/2, on the
+    // block's own progression), and the walk goes forward and backward from it, so no
+    // frequency is more than W/2 steps from its seed (the rounding of w, or of 2 Re(w),
+    // enters once per step).
     constexpr int KS = DIRECT ? 0 : W / 2;
     const double om_seed = om_first + (double)KS * (BSTEP ? bstep : j.domega);
     // explicit frequencies (direct phase) and direction-dependent shape factors of this lane
@@ -164,7 +169,8 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
 #pragma unroll 8
             for (int m = 0; m < P; ++m, dst += TO) {
                 const float2 N = nw[m];
-                *dst = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
+                const float Fo = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
+                *dst = (TT && (o & 2)) ? -Fo : Fo;
             }
         }
         __syncthreads();
@@ -242,15 +248,63 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                         add(k, Fv[u], zr, zi);
                     }
                 }
+            } else if constexpr (TT) {
+                // z_{k+1} = c z_k - z_{k-1} with c = 2 cos(theta) = 2 Re(w), theta = domega tau,
+                // forward from (z_8, z_9 = z_8 w) and backward from (z_8, z_7 = z_8 conj(w)).
+                // To make every step one multiply-add per component without a negation the
+                // lane walks y_k = sigma_k z_k, sigma = (+, +, -, -) by k mod 4 (the F table
+                // holds sigma_k F_k, so the scaled term is F_k z_k):
+                //   forward   y_{k+1} = c_k y_k + y_{k-1},  c_k = +c (k even), -c (k odd);
+                //   backward  y_{k-1} = c'_k y_k + y_{k+1}, c'_k = -c (k even), +c (k odd).
+                // Accuracy: a perturbation e of one step reaches m steps later as
+                // e sin(m theta) / sin(theta), at most m e in size, so the rounding of c
+                // (about 2^-23) and of each step gives at most ~m^2 ulps after m <= 7 steps
+                // -- a few 1e-6 of |z| = 1, also for theta near 0 or pi.  The mid-block seed
+                // (short walks) and the accurate w keep this close to the product walk's
+                // error; a 15-step walk from one end of the block, or a hardware-quality
+                // cos(theta), would lose one to two more decimal digits.
+                const float cc = 2.f * wr;
+                float pc = cc, nc = -cc, nwi = -wi, nwr = -wr;
+                asm volatile("" : "+v"(pc), "+v"(nc), "+v"(nwi), "+v"(nwr));
+                float Fh[16];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float Fv[4];
+                    weights(q, Fv);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) Fh[4 * q + u] = Fv[u];
+                }
+                // forward: (pr, pi) = y_{k-1}, (cr, ci) = y_k
+                float pr = zr, pi = zi;                                          // y8
+                float cr = fmaf(zr, wr, zi * nwi), ci = fmaf(zr, wi, zi * wr);   // y9 = z w
+                add(8, Fh[8], pr, pi);
+                add(9, Fh[9], cr, ci);
+#pragma unroll
+                for (int k = 9; k < 15; ++k) {
+                    const float ck = (k & 1) ? nc : pc;
+                    const float nr = fmaf(ck, cr, pr), ni = fmaf(ck, ci, pi);
+                    pr = cr; pi = ci; cr = nr; ci = ni;
+                    add(k + 1, Fh[k + 1], cr, ci);
+                }
+                // backward: (pr, pi) = y_{k+1}, (cr, ci) = y_k; y7 = -(z conj(w))
+                pr = zr; pi = zi;
+                cr = fmaf(zr, nwr, zi * nwi); ci = fmaf(zr, wi, zi * nwr);
+                add(7, Fh[7], cr, ci);
+#pragma unroll
+                for (int k = 7; k > 0; --k) {
+                    const float ck = (k & 1) ? pc : nc;
+                    const float nr = fmaf(ck, cr, pr), ni = fmaf(ck, ci, pi);
+                    pr = cr; pi = ci; cr = nr; ci = ni;
+                    add(k - 1, Fh[k - 1], cr, ci);
+                }
             } else {
                 // Uniform steps (or a block's own step): z_{k+1} = z_k w forward from the seed
                 // and z_{k-1} = z_k conj(w) backward from it -- complex products, two products
-                // and two multiply-adds per frequency.  Their error grows by about one
-                // rounding of w per product whatever theta = domega tau is (a three-term
-                // recurrence 2 cos(theta) z_k - z_{k-1} is cheaper but divides the rounding of
-                // 2 cos(theta) by sin(theta), which ruins terms whose step is near 0 or pi).
-                // The opaque negation keeps every operation a VOP2 product or multiply-add
-                // without source modifiers.
+                // and two multiply-adds per frequency, whose error grows by about one rounding
+                // of w per product.  Used where the three-term walk is not: 32 frequencies
+                // per lane (walks of 16 steps), block-stepped lists, cubic cells, the FP32
+                // geometry variant.  The opaque negation keeps every operation a VOP2 product
+                // or multiply-add without source modifiers.
                 float nwi = -wi;
                 asm volatile("" : "+v"(nwi));
                 float fr = zr, fi = zi;

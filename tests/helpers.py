@@ -38,9 +38,9 @@ def oracle_samples(steps: dict, times) -> dict:
 def in_block_sample(n: int, stride: int = 16, offsets=(0, 7, 15)) -> np.ndarray:
     """Frequency indices for sampled parity: in every block of `stride` frequencies the
     given offsets, plus the last frequency.  A 16-frequency lane is seeded from FP64 at its
-    offset 8 and walks to the others by complex products: the default offsets are the
-    farthest walked backward (0, eight products), the nearest (7, one) and the farthest
-    forward (15, seven)."""
+    offset 8 and walks to the others (three-term recurrence or complex products): the default
+    offsets are the farthest walked backward (0, eight steps), the nearest (7, one) and the
+    farthest forward (15, seven)."""
     ks = [np.arange(o, n, stride) for o in offsets]
     return np.unique(np.concatenate(ks + [np.array([n - 1])]))
 

@@ -359,10 +359,11 @@ def test_device_readout_is_ordered_before_later_reset_and_push(rad):
 
 
 def test_recurrence_with_steps_near_zero_and_pi(rad):
-    """A frequency recurrence loses the most accuracy when the per-frequency phase step
-    domega*tau is close to a multiple of pi: the three-term form 2 cos(theta) z_k - z_{k-1}
-    drifts there (the rounding of 2 cos(theta) is divided by sin(theta)); the kernel's
-    complex-product walk must not.  Particles
+    """The per-frequency phase step theta = domega*tau close to a multiple of pi is the hard
+    case for the three-term walk z_{k+1} = 2 cos(theta) z_k - z_{k-1} of the uniform-grid
+    kernel: there the rounding of 2 cos(theta) stands for a large angle error, and only the
+    short walks from the mid-block seed (at most 8 steps, error at most ~m^2 roundings) keep
+    it small.  Every frequency is checked.  Particles
     are placed so that on the axis the step is within 1e-7..1e-2 rad of 0 or pi (and within
     ~0.02 rad of it on the tilted directions); three steps a whole number of step periods
     apart."""
