@@ -21,10 +21,11 @@
 //     4. the hot loop: per particle, each lane seeds z = exp(i omega tau) at the middle
 //        frequency of its block from the FP64 phase (reduced to [0, 1) revolutions before
 //        leaving FP64), then walks its W frequencies forward and backward from it, scaling
-//        by F and accumulating.  On a uniform grid with 16 frequencies per lane the walk is
-//        the three-term recurrence z_{k+1} = 2 cos(theta) z_k - z_{k-1}: 8 FP32 VALU
-//        operations per update, 2 (scale) + 4 (two complex multiply-adds) + 2 (recurrence).
-//        Other layouts walk by complex products with w: 10 per update (4 for the rotation).
+//        by F and accumulating.  With 16 frequencies per lane on uniform steps (grid-wide
+//        or per block) the walk is the three-term recurrence z_{k+1} = 2 cos(theta) z_k -
+//        z_{k-1}: 8 FP32 VALU operations per update, 2 (scale) + 4 (two complex
+//        multiply-adds) + 2 (recurrence).  32-frequency lanes walk by complex products with
+//        w: 10 per update (4 for the rotation).
 // * At the end each workgroup writes its FP32 partial tile; a fold kernel adds the splits
 //   in a fixed order in FP64 into the grid's FP64 accumulator (deterministic).
 
@@ -79,9 +80,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
     constexpr bool BSTEP = (V & kVarBlockStep) != 0;
     static_assert(!(DIRECT && BSTEP), "a frequency list is either direct or block-stepped");
     static_assert(!BSTEP || W == kBlockW, "block steps are defined per 16 frequencies");
-    // uniform grid, 1-D shape, FP64 geometry, 16 frequencies per lane: the walk is the
-    // three-term recurrence from the mid-block seed (at most 7 steps from it)
-    constexpr bool TT = (V == 0) && (W == 16) && (PREC == 0);
+    // uniform steps (grid-wide or per block), FP64 geometry, 16 frequencies per lane: the
+    // walk is the three-term recurrence from the mid-block seed (at most 8 steps from it)
+    constexpr bool TT = !DIRECT && (W == 16) && (PREC == 0);
     const int d = td * TD + dl;
     const int o_first = tw * TO + ob * W;
     const double om_first = gload(j.omega, o_first < j.n_omega ? o_first : j.n_omega - 1);
@@ -170,7 +171,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
             for (int m = 0; m < P; ++m, dst += TO) {
                 const float2 N = nw[m];
                 const float Fo = __builtin_amdgcn_sqrtf(fmaf(N.y, g.x, N.x * g.y));
-                *dst = (TT && (o & 2)) ? -Fo : Fo;
+                *dst = (TT && (o & 2)) ? -Fo : Fo;   // sigma_k of the three-term walk
             }
         }
         __syncthreads();
@@ -220,13 +221,23 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     Fv[0] = F4.x; Fv[1] = F4.y; Fv[2] = F4.z; Fv[3] = F4.w;
                 }
             };
+            // The three-term walk's sign factors sigma_k (below) ride on the F table; a
+            // per-update F (cubic cells) has no table, so there they ride on A instead.
+            float nA1 = 0.f, nA2 = 0.f;
+            if constexpr (TT && SHAPE3) {
+                nA1 = -A1;
+                nA2 = -A2;
+                asm volatile("" : "+v"(nA1), "+v"(nA2));
+            }
             // S(k) += F A exp(i omega_k tau): 2 products and 4 multiply-adds
             auto add = [&](int k, float F, float xr, float xi) {
                 const float ur = F * xr, ui = F * xi;
-                s1r[k] = fmaf(A1, ur, s1r[k]);
-                s1i[k] = fmaf(A1, ui, s1i[k]);
-                s2r[k] = fmaf(A2, ur, s2r[k]);
-                s2i[k] = fmaf(A2, ui, s2i[k]);
+                const float a1 = (TT && SHAPE3 && (k & 2)) ? nA1 : A1;
+                const float a2 = (TT && SHAPE3 && (k & 2)) ? nA2 : A2;
+                s1r[k] = fmaf(a1, ur, s1r[k]);
+                s1i[k] = fmaf(a1, ui, s1i[k]);
+                s2r[k] = fmaf(a2, ur, s2r[k]);
+                s2i[k] = fmaf(a2, ui, s2i[k]);
             };
             if constexpr (DIRECT) {
                 // explicit frequency list: each term's phase from the FP64 product, reduced to
@@ -253,7 +264,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 // forward from (z_8, z_9 = z_8 w) and backward from (z_8, z_7 = z_8 conj(w)).
                 // To make every step one multiply-add per component without a negation the
                 // lane walks y_k = sigma_k z_k, sigma = (+, +, -, -) by k mod 4 (the F table
-                // holds sigma_k F_k, so the scaled term is F_k z_k):
+                // holds sigma_k F_k, or A is negated, so the accumulated term is F_k A z_k):
                 //   forward   y_{k+1} = c_k y_k + y_{k-1},  c_k = +c (k even), -c (k odd);
                 //   backward  y_{k-1} = c'_k y_k + y_{k+1}, c'_k = -c (k even), +c (k odd).
                 // Accuracy: a perturbation e of one step reaches m steps later as
@@ -302,9 +313,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 // and z_{k-1} = z_k conj(w) backward from it -- complex products, two products
                 // and two multiply-adds per frequency, whose error grows by about one rounding
                 // of w per product.  Used where the three-term walk is not: 32 frequencies
-                // per lane (walks of 16 steps), block-stepped lists, cubic cells, the FP32
-                // geometry variant.  The opaque negation keeps every operation a VOP2 product
-                // or multiply-add without source modifiers.
+                // per lane (walks of 16 steps) and the FP32 geometry variant (whose w comes
+                // from the hardware sin/cos).  The opaque negation keeps every operation a
+                // VOP2 product or multiply-add without source modifiers.
                 float nwi = -wi;
                 asm volatile("" : "+v"(nwi));
                 float fr = zr, fi = zi;

@@ -26,7 +26,7 @@ namespace {
 // frequency blocks), TD = NT / OB.  The steps of a push are taken S = OB at a
 // time: the S x TD (step, direction) geometries (FP64, as in the main path) are computed
 // once, one per thread, into LDS, then every thread walks its W frequencies for each of the
-// S steps with the main path's complex-product walk from the block's middle frequency (or,
+// S steps with the main path's three-term walk from the block's middle frequency (or,
 // for explicit frequency lists, the per-term FP64 phase).  The per-(step, direction) set-up is thus shared by OB * W
 // frequencies.  Up to kStepGroup steps of one push are summed in FP32 registers before one
 // read-modify-write of the FP64 integrals, so a multi-step push moves 64 B per particle and
@@ -137,11 +137,20 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
             for (int s = 0; s < ns; ++s) {
                 const float4 gv = geo[s * TD + dl];
                 const double ph = tau[s * TD + dl];
+                // the three-term walk's sign factors sigma_k ride on A (nA = -A)
+                float nA1 = 0.f, nA2 = 0.f;
+                if constexpr (!DIRECT) {
+                    nA1 = -gv.x;
+                    nA2 = -gv.y;
+                    asm volatile("" : "+v"(nA1), "+v"(nA2));
+                }
                 auto add = [&](int k, float xr, float xi) {
-                    acc[k].x = fmaf(gv.x, xr, acc[k].x);
-                    acc[k].y = fmaf(gv.x, xi, acc[k].y);
-                    acc[k].z = fmaf(gv.y, xr, acc[k].z);
-                    acc[k].w = fmaf(gv.y, xi, acc[k].w);
+                    const float a1 = (!DIRECT && (k & 2)) ? nA1 : gv.x;
+                    const float a2 = (!DIRECT && (k & 2)) ? nA2 : gv.y;
+                    acc[k].x = fmaf(a1, xr, acc[k].x);
+                    acc[k].y = fmaf(a1, xi, acc[k].y);
+                    acc[k].z = fmaf(a2, xr, acc[k].z);
+                    acc[k].w = fmaf(a2, xi, acc[k].w);
                 };
                 if constexpr (DIRECT) {
 #pragma unroll
@@ -151,30 +160,37 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
                         add(k, zr, zi);
                     }
                 } else {
-                    // the main path's walk: complex products with w forward and with conj(w)
-                    // backward from the seed at frequency KS
+                    // the main path's three-term walk on y_k = sigma_k z_k, sigma = (+, +, -, -)
+                    // by k mod 4, from the seed at frequency KS (a multiple of 4, so y_KS = z):
+                    // forward from (y_KS, y_KS+1 = z w) by y_{k+1} = c_k y_k + y_{k-1}, backward
+                    // from (y_KS, y_KS-1 = -z conj(w)) by y_{k-1} = c'_k y_k + y_{k+1};
+                    // c = 2 Re(w), c_k = +c / -c and c'_k = -c / +c for even / odd k
+                    static_assert(KS % 4 == 0, "the sign pattern assumes y_KS = y_KS+1 = +z");
                     float zr, zi;
                     sincos_rev_fast(static_cast<float>(frac_rev(om_seed * ph)), zi, zr);
                     const float wr = gv.z, wi = gv.w;
-                    float nwi = -wi;
-                    asm volatile("" : "+v"(nwi));
-                    float fr = zr, fi = zi;
+                    float pc = 2.f * wr, nc = -2.f * wr, nwi = -wi, nwr = -wr;
+                    asm volatile("" : "+v"(pc), "+v"(nc), "+v"(nwi), "+v"(nwr));
+                    float pr = zr, pi = zi;
+                    float cr = fmaf(zr, wr, zi * nwi), ci = fmaf(zr, wi, zi * wr);
+                    add(KS, pr, pi);
+                    add(KS + 1, cr, ci);
 #pragma unroll
-                    for (int k = KS; k < W; ++k) {
-                        add(k, fr, fi);
-                        if (k + 1 < W) {
-                            const float nr = fmaf(fr, wr, fi * nwi), ni = fmaf(fr, wi, fi * wr);
-                            fr = nr;
-                            fi = ni;
-                        }
+                    for (int k = KS + 1; k < W - 1; ++k) {
+                        const float ck = (k & 1) ? nc : pc;
+                        const float nr = fmaf(ck, cr, pr), ni = fmaf(ck, ci, pi);
+                        pr = cr; pi = ci; cr = nr; ci = ni;
+                        add(k + 1, cr, ci);
                     }
-                    float br = zr, bi = zi;
+                    pr = zr; pi = zi;
+                    cr = fmaf(zr, nwr, zi * nwi); ci = fmaf(zr, wi, zi * nwr);
+                    add(KS - 1, cr, ci);
 #pragma unroll
-                    for (int k = KS - 1; k >= 0; --k) {
-                        const float nr = fmaf(br, wr, bi * wi), ni = fmaf(bi, wr, br * nwi);
-                        br = nr;
-                        bi = ni;
-                        add(k, br, bi);
+                    for (int k = KS - 1; k > 0; --k) {
+                        const float ck = (k & 1) ? pc : nc;
+                        const float nr = fmaf(ck, cr, pr), ni = fmaf(ck, ci, pi);
+                        pr = cr; pi = ci; cr = nr; ci = ni;
+                        add(k - 1, cr, ci);
                     }
                 }
             }

@@ -33,6 +33,7 @@ def test_batched_profile_matches_sources_and_tuned_shape():
     vals = machine_lines("k_accumulate_batch_batched_uneven.md")
     assert vals["kernel_source_sha256"] == source_sha256(ACCUMULATE_FILES)
     tile = lookup_batch(64, 256, 0)
+    assert vals["tile"] == ",".join(str(tile[k]) for k in ("w_per_lane", "dir_per_wave", "waves", "wg_per_cu"))
     got = bench.profile_values("k_accumulate_batch_batched_uneven.md", tile)
     assert got["traffic_bytes_per_launch"] > 0
 

@@ -1,7 +1,8 @@
-"""FP32 accuracy of the two frequency walks of the accumulate kernel (FP32 emulation on the CPU,
-no GPU).  A lane reaches exp(i(s + k) theta), k = 0..15, theta the per-frequency phase step,
-from an FP32 seed at k = 8 (the middle of its block) and the rotation w = exp(i theta) rounded
-once to FP32.
+"""FP32 accuracy of the two frequency walks of the kernels (FP32 emulation on the CPU, no
+GPU).  A lane of the accumulate kernel reaches exp(i(s + k) theta), k = 0..15, theta the
+per-frequency phase step, from an FP32 seed at k = 8 (the middle of its block) and the
+rotation w = exp(i theta) rounded once to FP32; a thread of the tracked-particle kernel does
+the same over k = 0..7 from k = 4.
 
 * Complex-product walk (z <- z w forward, z <- z conj(w) backward): about one rounding of w
   per product, so a few ulps after at most 8 products, whatever theta is.
@@ -67,31 +68,34 @@ def sigma(k):
     return -1.0 if k & 2 else 1.0
 
 
-def walk_three_term_mid(theta, phase0, flip_sigma=False):
-    """The kernel's three-term walk on y_k = sigma_k z_k from (y_8, y_9 = z w) forward and
-    (y_8, y_7 = -z conj(w)) backward; returns z_k = sigma_k y_k."""
-    zr, zi, wr, wi = seed_and_w(theta, phase0, 8)
+def walk_three_term_mid(theta, phase0, flip_sigma=False, W=16):
+    """The kernels' three-term walk on y_k = sigma_k z_k over W frequencies (16 in the
+    accumulate kernel, 8 in the tracked-particle kernel) from the seed at s = W/2: forward
+    from (y_s, y_s+1 = z w), backward from (y_s, y_s-1 = -z conj(w)); returns
+    z_k = sigma_k y_k."""
+    ks = W // 2
+    zr, zi, wr, wi = seed_and_w(theta, phase0, ks)
     pc = (f32(2) * wr).astype(f32)          # exact doubling
     nc = -pc
-    y = [None] * 16
+    y = [None] * W
     pr, pi = zr, zi
     cr, ci = fma(zr, wr, mul(zi, -wi)), fma(zr, wi, mul(zi, wr))
-    y[8], y[9] = (pr, pi), (cr, ci)
-    for k in range(9, 15):
+    y[ks], y[ks + 1] = (pr, pi), (cr, ci)
+    for k in range(ks + 1, W - 1):
         ck = nc if k & 1 else pc
         nr, ni = fma(ck, cr, pr), fma(ck, ci, pi)
         pr, pi, cr, ci = cr, ci, nr, ni
         y[k + 1] = (cr, ci)
     pr, pi = zr, zi
     cr, ci = fma(zr, -wr, mul(zi, -wi)), fma(zr, wi, mul(zi, -wr))
-    y[7] = (cr, ci)
-    for k in range(7, 0, -1):
+    y[ks - 1] = (cr, ci)
+    for k in range(ks - 1, 0, -1):
         ck = pc if k & 1 else nc
         nr, ni = fma(ck, cr, pr), fma(ck, ci, pi)
         pr, pi, cr, ci = cr, ci, nr, ni
         y[k - 1] = (cr, ci)
     s = (lambda k: 1.0 if (k & 1) else sigma(k)) if flip_sigma else sigma
-    return np.stack([s(k) * cplx(*y[k]) for k in range(16)])
+    return np.stack([s(k) * cplx(*y[k]) for k in range(W)])
 
 
 def walk_three_term_from_start(theta, phase0):
@@ -110,8 +114,8 @@ def walk_three_term_from_start(theta, phase0):
     return out
 
 
-def exact(theta, phase0):
-    k = np.arange(16)[:, None]
+def exact(theta, phase0, W=16):
+    k = np.arange(W)[:, None]
     return np.exp(1j * (phase0 + k * theta))
 
 
@@ -136,6 +140,14 @@ def test_mid_seeded_three_term_walk_within_its_m_squared_bound():
     bound = (4 + 2 * m + m * m) * ULP
     assert (err <= bound).all(), (err / bound).max()
     assert err.max() < 6e-6, err.max()
+
+
+def test_tracked_kernel_three_term_walk_over_8_frequencies():
+    theta, phase0 = inputs(10)
+    err = np.abs(walk_three_term_mid(theta, phase0, W=8) - exact(theta, phase0, W=8))
+    m = np.abs(np.arange(8) - 4)[:, None]
+    assert (err <= (4 + 2 * m + m * m) * ULP).all()
+    assert err.max() < 2e-6, err.max()
 
 
 def test_three_term_walk_is_not_amplified_near_zero_and_pi():
