@@ -261,7 +261,7 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 }
             } else if constexpr (TT) {
                 // z_{k+1} = c z_k - z_{k-1} with c = 2 cos(theta) = 2 Re(w), theta = domega tau,
-                // forward from (z_8, z_9 = z_8 w) and backward from (z_8, z_7 = z_8 conj(w)).
+                // forward from (z_8, z_9 = z_8 w) and backward from (z_8, z_7 = c z_8 - z_9).
                 // To make every step one multiply-add per component without a negation the
                 // lane walks y_k = sigma_k z_k, sigma = (+, +, -, -) by k mod 4 (the F table
                 // holds sigma_k F_k, or A is negated, so the accumulated term is F_k A z_k):
@@ -274,9 +274,10 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 // (short walks) and the accurate w keep this close to the product walk's
                 // error; a 15-step walk from one end of the block, or a hardware-quality
                 // cos(theta), would lose one to two more decimal digits.
-                const float cc = 2.f * wr;
-                float pc = cc, nc = -cc, nwi = -wi, nwr = -wr;
-                asm volatile("" : "+v"(pc), "+v"(nc), "+v"(nwi), "+v"(nwr));
+                // +c and -c each in a register of their own, so that every step is a VOP2
+                // multiply-add (no negation modifier, which needs the longer VOP3 form)
+                float pc = 2.f * wr, nc = -2.f * wr;
+                asm volatile("" : "+v"(pc), "+v"(nc));
                 float Fh[16];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -287,7 +288,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                 }
                 // forward: (pr, pi) = y_{k-1}, (cr, ci) = y_k
                 float pr = zr, pi = zi;                                          // y8
-                float cr = fmaf(zr, wr, zi * nwi), ci = fmaf(zr, wi, zi * wr);   // y9 = z w
+                float cr = fmaf(zr, wr, -(zi * wi)), ci = fmaf(zr, wi, zi * wr); // y9 = z w
+                // y7 = -z_7 = -(c z_8 - z_9) = -c y8 + y9: one multiply-add per component
+                const float y7r = fmaf(nc, zr, cr), y7i = fmaf(nc, zi, ci);
                 add(8, Fh[8], pr, pi);
                 add(9, Fh[9], cr, ci);
 #pragma unroll
@@ -297,9 +300,9 @@ __device__ __forceinline__ void accumulate_range(const Job& j, int td, int tw, i
                     pr = cr; pi = ci; cr = nr; ci = ni;
                     add(k + 1, Fh[k + 1], cr, ci);
                 }
-                // backward: (pr, pi) = y_{k+1}, (cr, ci) = y_k; y7 = -(z conj(w))
+                // backward: (pr, pi) = y_{k+1}, (cr, ci) = y_k
                 pr = zr; pi = zi;
-                cr = fmaf(zr, nwr, zi * nwi); ci = fmaf(zr, wi, zi * nwr);
+                cr = y7r; ci = y7i;
                 add(7, Fh[7], cr, ci);
 #pragma unroll
                 for (int k = 7; k > 0; --k) {

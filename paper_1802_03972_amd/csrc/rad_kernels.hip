@@ -163,16 +163,17 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
                     // the main path's three-term walk on y_k = sigma_k z_k, sigma = (+, +, -, -)
                     // by k mod 4, from the seed at frequency KS (a multiple of 4, so y_KS = z):
                     // forward from (y_KS, y_KS+1 = z w) by y_{k+1} = c_k y_k + y_{k-1}, backward
-                    // from (y_KS, y_KS-1 = -z conj(w)) by y_{k-1} = c'_k y_k + y_{k+1};
+                    // from (y_KS, y_KS-1 = -c y_KS + y_KS+1) by y_{k-1} = c'_k y_k + y_{k+1};
                     // c = 2 Re(w), c_k = +c / -c and c'_k = -c / +c for even / odd k
                     static_assert(KS % 4 == 0, "the sign pattern assumes y_KS = y_KS+1 = +z");
                     float zr, zi;
                     sincos_rev_fast(static_cast<float>(frac_rev(om_seed * ph)), zi, zr);
                     const float wr = gv.z, wi = gv.w;
-                    float pc = 2.f * wr, nc = -2.f * wr, nwi = -wi, nwr = -wr;
-                    asm volatile("" : "+v"(pc), "+v"(nc), "+v"(nwi), "+v"(nwr));
+                    float pc = 2.f * wr, nc = -2.f * wr;
+                    asm volatile("" : "+v"(pc), "+v"(nc));
                     float pr = zr, pi = zi;
-                    float cr = fmaf(zr, wr, zi * nwi), ci = fmaf(zr, wi, zi * wr);
+                    float cr = fmaf(zr, wr, -(zi * wi)), ci = fmaf(zr, wi, zi * wr);
+                    const float ybr = fmaf(nc, zr, cr), ybi = fmaf(nc, zi, ci);
                     add(KS, pr, pi);
                     add(KS + 1, cr, ci);
 #pragma unroll
@@ -183,7 +184,7 @@ __global__ void __launch_bounds__(NT, RAD_TRACK_WAVES) k_tracked_accumulate(Trac
                         add(k + 1, cr, ci);
                     }
                     pr = zr; pi = zi;
-                    cr = fmaf(zr, nwr, zi * nwi); ci = fmaf(zr, wi, zi * nwr);
+                    cr = ybr; ci = ybi;
                     add(KS - 1, cr, ci);
 #pragma unroll
                     for (int k = KS - 1; k > 0; --k) {

@@ -71,8 +71,8 @@ def sigma(k):
 def walk_three_term_mid(theta, phase0, flip_sigma=False, W=16):
     """The kernels' three-term walk on y_k = sigma_k z_k over W frequencies (16 in the
     accumulate kernel, 8 in the tracked-particle kernel) from the seed at s = W/2: forward
-    from (y_s, y_s+1 = z w), backward from (y_s, y_s-1 = -z conj(w)); returns
-    z_k = sigma_k y_k."""
+    from (y_s, y_s+1 = z w), backward from (y_s, y_s-1 = -c y_s + y_s+1, i.e.
+    -(c z_s - z_s+1)); returns z_k = sigma_k y_k."""
     ks = W // 2
     zr, zi, wr, wi = seed_and_w(theta, phase0, ks)
     pc = (f32(2) * wr).astype(f32)          # exact doubling
@@ -81,14 +81,14 @@ def walk_three_term_mid(theta, phase0, flip_sigma=False, W=16):
     pr, pi = zr, zi
     cr, ci = fma(zr, wr, mul(zi, -wi)), fma(zr, wi, mul(zi, wr))
     y[ks], y[ks + 1] = (pr, pi), (cr, ci)
+    y[ks - 1] = (fma(nc, zr, cr), fma(nc, zi, ci))
     for k in range(ks + 1, W - 1):
         ck = nc if k & 1 else pc
         nr, ni = fma(ck, cr, pr), fma(ck, ci, pi)
         pr, pi, cr, ci = cr, ci, nr, ni
         y[k + 1] = (cr, ci)
     pr, pi = zr, zi
-    cr, ci = fma(zr, -wr, mul(zi, -wi)), fma(zr, wi, mul(zi, -wr))
-    y[ks - 1] = (cr, ci)
+    cr, ci = y[ks - 1]
     for k in range(ks - 1, 0, -1):
         ck = pc if k & 1 else nc
         nr, ni = fma(ck, cr, pr), fma(ck, ci, pi)
