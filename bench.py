@@ -812,6 +812,20 @@ def bench_tracked(args) -> dict:
     stream = torch.cuda.current_stream(0)
     wts = st["w"][0]
 
+    # for comparison, 100 one-step pushes, timed first (events bracket only the pushes; the
+    # reset fill runs before the first event); the read-out below is of the last 100-step push
+    def timed_one_step_pushes():
+        tr.reset(stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for j in range(w.n_steps):
+            tr.push_step(float(times[j]), slices[j], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    single_ms = None if args.skip_one_step else timed_one_step_pushes() / w.n_steps
+
     def pushes():
         tr.reset(stream)
         tr.push_steps(float(times[0]), w.n_steps, dev, stream)
@@ -819,35 +833,25 @@ def bench_tracked(args) -> dict:
     for _ in range(max(1, args.warmup)):
         pushes()
     torch.cuda.synchronize()
+    # the accumulate launch of every timed push is bracketed by its own events (the reset's
+    # fill runs before the first one); the launches run back to back, as in the whole job
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
-        pushes()
+    for ka, kb in kev:
+        tr.reset(stream)
+        ka.record(stream)
+        tr.push_steps(float(times[0]), w.n_steps, dev, stream)
+        kb.record(stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) * 1e-3)
     updates = n * w.n_dir * w.n_omega * w.n_steps
     value = updates * args.steps / elapsed
+    launch_ms = sum(ka.elapsed_time(kb) for ka, kb in kev) / len(kev)
 
-    # duration of the accumulate kernel alone: the 100-step push (one launch) and, for
-    # comparison, 100 one-step pushes (events bracket only the pushes; the reset fill runs
-    # before the first event)
-    def timed_push(multi):
-        tr.reset(stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        if multi:
-            tr.push_steps(float(times[0]), w.n_steps, dev, stream)
-        else:
-            for j in range(w.n_steps):
-                tr.push_step(float(times[j]), slices[j], stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1)
-    single_ms = None if args.skip_one_step else timed_push(False) / w.n_steps
-    launch_ms = timed_push(True)
     group = rad.Tracked.step_group()
     groups = -(-w.n_steps // group)
     points = n * w.n_dir * w.n_omega
