@@ -790,10 +790,11 @@ def bench_tracked(args) -> dict:
     """Post-processing variant: 1024 tracked particles x 100 steps of the single-bunch
     generator on its 128 x 256 grid; each step adds every particle's term into its own FP64
     time integral (read-modify-write of 32 B per particle and grid point), and the read-out
-    applies weights and shape afterwards.  The timed push hands all 100 steps to one launch,
-    which sums up to `Tracked.step_group()` (128) steps in registers before each
-    read-modify-write of the integrals (64 B per particle and grid point per group);
-    one-step pushes (64 B per update, HBM-bound) are timed beside it."""
+    applies weights and shape afterwards.  Each timed push (a reset, then all 100 steps in one
+    launch) sums up to `Tracked.step_group()` (128) steps in registers before each
+    read-modify-write of the integrals (64 B per particle and grid point per group); the
+    launches are timed one by one with events and averaged.  One-step pushes (64 B per
+    update, HBM-bound) are timed first, for comparison."""
     import numpy as np
     import torch
 
