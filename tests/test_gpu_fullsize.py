@@ -34,7 +34,9 @@ def grid_for(rad, w, **kw):
 
 def test_single_bunch_all_100_steps(rad):
     """65536 particles x 100 per-step pushes on 128 x 256 with the tuned launch shape;
-    oracle on every 8th direction x frequencies 0, 7, 15 of every block of 16."""
+    oracle on every 8th direction x frequencies 0, 7, 15 of every block of 16, and on two
+    directions x every frequency (all 16 in-block offsets of the walk, up to eight steps
+    from the seed)."""
     w = SINGLE
     st = w.steps(workers=host_workers())
     dev = to_device(st, "f32")
@@ -42,10 +44,16 @@ def test_single_bunch_all_100_steps(rad):
     for j, t in enumerate(w.times()):
         g.push_step(float(t), step_slice(dev, j, w.n_particles))
     I = g.spectrum()
+    parts = flatten(st, w.times())
     ds = np.arange(0, w.n_dir, 8)
     ks = in_block_sample(w.n_omega)
-    Iref = oracle.spectrum(flatten(st, w.times()), w.directions()[ds], w.omegas()[ks], w.shape, w.shape_len, w.dt)
+    Iref = oracle.spectrum(parts, w.directions()[ds], w.omegas()[ks], w.shape, w.shape_len, w.dt)
     assert_parity(I[np.ix_(ds, ks)], Iref, f"single bunch, 100 steps, tile {g.get_tile()}", ks=ks)
+    d2 = np.array([0, 77])
+    ka = np.arange(w.n_omega)
+    Iref2 = oracle.spectrum(parts, w.directions()[d2], w.omegas(), w.shape, w.shape_len, w.dt)
+    # the report lists the per-frequency error by in-block offset (k mod 16)
+    assert_parity(I[d2], Iref2, "single bunch, 100 steps, two directions x every frequency", ks=ka)
 
 
 PRECISION_KS = np.array([0, 1, 7, 15, 135, 271, 392, 519, 655, 776, 903, 1015, 1023])
